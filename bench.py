@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark: click correlators and cumulants of all subsets of order <= 5 at M = 144.
+
+One step = one full pass of the path on the resident covariance: Q = sigma + I/2
+(and, for the mixed form, its per-mode normalisation), then orders 1..5 of
+vacuum probabilities -> correlators -> cumulants, every output written to HBM.
+498,685,188 subsets per step.  Prints ONE JSON line.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--precision fp64|mixed]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+M = 144
+K = 5
+# algorithmic flops per order-d subset: one new 2d x 2d factorisation, (2d)^3/3,
+# plus 2^(d+1) for inclusion-exclusion and the cumulant recursion
+FLOPS_PER_SUBSET = {d: (2 * d) ** 3 / 3 + 2 ** (d + 1) for d in range(1, 6)}
+PEAK_VALU_TFLOPS = 78.6  # one non-packed FMA per lane per clock: 256 CU x 64 lanes x 2 x 2.4 GHz
+WORKLOAD = ("m144_k5: M=144 modes, subsets of order 1..5 (498,685,188), Haar interferometer, "
+            "x-squeezing r~U[0.6,1.6], input loss eta~U[0.25,0.4], xxpp, hbar=1")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_forward_order5_m144.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2511_14923_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_precision(P, torch, sigma, corr, cum, flags, steps, warmup, label):
+    for i in range(warmup):
+        P.gbs_cumulants(M, sigma, K, flags, corr=corr, cum=cum)
+        log(f"[bench] {label} warmup {i + 1}/{warmup} done")
+    torch.cuda.synchronize()
+    kern = {d: [] for d in range(1, K + 1)}
+    t0 = time.perf_counter()
+    for i in range(steps):
+        P.gbs_cumulants(M, sigma, K, flags | P.GBS_TIMING, corr=corr, cum=cum)
+        for stage, order, ms in P.gbs_last_timings():
+            if stage == "forward":
+                kern[order].append(ms)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    log(f"[bench] {label}: {steps} steps in {t:.3f} s")
+    ms_step = 1e3 * t / steps
+    n = sum(math.comb(M, d) for d in range(1, K + 1))
+    k5 = sum(kern[5]) / len(kern[5])
+    flops5 = math.comb(M, 5) * FLOPS_PER_SUBSET[5]
+    return {
+        "ms_per_step": ms_step,
+        "subsets_per_s": n / (ms_step * 1e-3),
+        "kernel_ms": {d: sum(v) / len(v) for d, v in kern.items()},
+        "order5_kernel_ms": k5,
+        "order5_tflops": flops5 / (k5 * 1e-3) / 1e12,
+    }
+
+
+def traffic_entry(label):
+    """HBM bytes per order-5 launch from the committed rocprofv3 counter runs,
+    or None when missing or taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(label)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def precision_errors(torch, P, corr64, cum64, corrmx, cummx):
+    out = {}
+    for d in range(1, K + 1):
+        a, b = P.gbs_order_offset(M, d), P.gbs_order_offset(M, d + 1)
+        for name, x, y in (("corr", corrmx, corr64), ("cum", cummx, cum64)):
+            dx = (x[a:b] - y[a:b]).abs()
+            ref = y[a:b].abs()
+            rel = dx / ref.clamp_min(1e-300)
+            q = torch.quantile(rel[:: max(1, rel.numel() // 1_000_000)].float(),
+                               torch.tensor([0.5, 0.99], device=rel.device)).tolist()
+            out[f"{name}_d{d}"] = {"normwise": float(dx.max() / ref.max()),
+                                   "rel_median": q[0], "rel_p99": q[1], "rel_max": float(rel.max())}
+    return out
+
+
+def fp64_parity_sample(np, O, G, inst, corr, cum, n=3000):
+    """Sampled FP64 outputs against the oracle: worst |delta| / tolerance."""
+    worst = 0.0
+    for d in range(1, K + 1):
+        cnt = math.comb(M, d)
+        ranks = G.random_ranks(cnt, min(n, cnt), seed=900 + d)
+        rc, rk = O.c_forward_sample(inst.sigma, d, ranks)
+        vmu, vkap = O.c_error_floor(inst.sigma, d, ranks)
+        off = O.order_offset(M, d)
+        gc = corr[off + ranks]
+        gk = cum[off + ranks]
+        for got, ref, v in ((gc, rc, vmu), (gk, rk, vkap)):
+            tol = 1e-10 * np.abs(ref) + O.FLOOR_FACTOR * O.U64 * v
+            worst = max(worst, float(np.max(np.abs(got - ref) / tol)))
+    return worst
+
+
+def cpu_baseline(np, O, G, inst, seconds):
+    """The C oracle on the host cores over a random sample of the workload's
+    subsets (all orders, in proportion to their counts)."""
+    threads = O.c_threads(0)
+    counts = [math.comb(M, d) for d in range(1, K + 1)]
+    total = sum(counts)
+
+    def run(n, seed):
+        rng = np.random.default_rng(seed)
+        picks = np.sort(rng.integers(0, total, size=n))
+        done = 0
+        t0 = time.perf_counter()
+        for d in range(1, K + 1):
+            a = sum(counts[: d - 1])
+            sel = picks[(picks >= a) & (picks < a + counts[d - 1])] - a
+            if len(sel):
+                O.c_forward_sample(inst.sigma, d, np.unique(sel), threads=threads)
+                done += len(np.unique(sel))
+        return done, time.perf_counter() - t0
+
+    n0, t0 = run(20000, 1)
+    n = int(min(5e7, max(20000, n0 / max(t0, 1e-3) * seconds)))
+    done, t = run(n, 2)
+    log(f"[bench] cpu oracle: {done} subsets in {t:.2f} s on {threads} threads")
+    return {"value": done / t, "unit": "subsets/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} subsets drawn uniformly from all 498,685,188 of the M=144 K=5 "
+                      f"workload (C oracle, OpenMP, {t:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="which form gives the headline value (both are measured)")
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
+                    help="measure one form only (profiling runs)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the path needs no communication and every "
+              "figure here is per GPU (see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gbs_inputs as G
+    import paper_2511_14923_amd as P
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    P.lib()
+    inst = G.make_instance("m144_k5")
+    sigma = torch.from_numpy(inst.sigma).to("cuda:0")
+    N = P.gbs_total_outputs(M, K)
+    log(f"[bench] M={M} K={K} outputs={N}")
+
+    forms = [args.only] if args.only else ["fp64", "mixed"]
+    res, bufs = {}, {}
+    for form in forms:
+        corr = torch.empty(N, dtype=torch.float64, device="cuda:0")
+        cum = torch.empty(N, dtype=torch.float64, device="cuda:0")
+        flags = P.GBS_MIXED if form == "mixed" else 0
+        res[form] = run_precision(P, torch, sigma, corr, cum, flags, args.steps, args.warmup, form)
+        bufs[form] = (corr, cum)
+
+    primary = args.precision if args.precision in res else forms[0]
+    r = res[primary]
+    extra = {}
+    if not args.no_check:
+        import oracle as O
+        if "fp64" in bufs:
+            c64 = bufs["fp64"][0].cpu().numpy()
+            k64 = bufs["fp64"][1].cpu().numpy()
+            extra["fp64_worst_err_over_tol"] = fp64_parity_sample(np, O, G, inst, c64, k64)
+            del c64, k64
+        if "fp64" in bufs and "mixed" in bufs:
+            extra["mixed_error_vs_fp64"] = precision_errors(torch, P, *bufs["fp64"], *bufs["mixed"])
+    base = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        base = cpu_baseline(np, O, G, inst, args.cpu_seconds)
+
+    flops5 = math.comb(M, 5) * FLOPS_PER_SUBSET[5]
+    traffic = traffic_entry(primary)
+    line = {
+        "metric": "order-<=5 cumulants/sec at M=144 (FP32-mixed vs FP64) at stated rel. error",
+        "value": r["subsets_per_s"],
+        "unit": "subsets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if primary == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "M": M, "max_order": K,
+                   "subsets": N, "precision": primary, "convention": "click"},
+        "roofline": {
+            "bound": "alu",
+            "kernel": f"forward order 5 ({primary})",
+            "achieved": r["order5_tflops"],
+            "peak": PEAK_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": r["order5_tflops"] / PEAK_VALU_TFLOPS,
+            "traffic": traffic,
+            "algorithmic_flops_per_launch": flops5,
+            "kernel_ms": r["order5_kernel_ms"],
+        },
+        "cpu_baseline": base,
+        "forms": res,
+    }
+    if "fp64" in res and "mixed" in res:
+        line["mixed_speedup_over_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * gbs.h -- click correlators and cumulants of a Gaussian state on MI355X (gfx950).
+ *
+ * C ABI of libgbs.  Plain pointers and sizes only.  Every compute entry point
+ * takes DEVICE pointers and runs its arithmetic in HIP kernels on `stream`
+ * (a hipStream_t; NULL means the null stream).  Helpers marked "host" take
+ * host pointers and launch nothing.
+ *
+ * Problem (arXiv 2511.14923, Sec. I.A and App. D.1): sigma is the 2M x 2M
+ * quadrature covariance of a zero-mean M-mode Gaussian state measured by
+ * threshold detectors, hbar = 1 (vacuum = I/2).  With Q = sigma + I/2 and Q_T
+ * the rows/columns k and k+M for k in T, the probability that every mode of T
+ * is in vacuum is
+ *        p(T) = det(Q_T)^(-1/2)          (Eqs. vacuum_gaussian_prob, correlator_sum_cov)
+ * and, for every subset S of the modes with 1 <= |S| <= max_order,
+ *   click correlator   mu(S)  = sum_{T subset S} (-1)^|T| p(T)
+ *                      (= probability that all of S click; App. A.2, Eq. joint_moments_def)
+ *   parity correlator  c(S)   = (-1)^|S| sum_{T subset S} (-2)^|T| p(T)
+ *                      (Sec. I.A, Eq. corre_cov_main)
+ *   cumulant           sum_{pi partition of S} (-1)^(|pi|-1) (|pi|-1)! prod_{B in pi} m(B)
+ *                      with m = mu (click cumulant kappa~, App. A.2, Eq. joint_cumulants_def)
+ *                      or m = c (cumulant kappa, Sec. I.A, Eq. cumulant_corr_main).
+ *
+ * Input layout: sigma is 2M x 2M FP64, row-major, xxpp ordering (index k is
+ * x_k, index k+M is p_k).  Only the lower triangle (row >= column) is read.
+ *
+ * Output layout (all output arrays): N(M, K) = sum_{d=1..K} C(M, d) FP64
+ * values; order blocks d = 1, 2, ..., K one after the other (block d starts at
+ * gbs_order_offset(M, d)); inside a block, subsets in colexicographic order:
+ * the subset {s_0 < s_1 < ... < s_{d-1}} has rank sum_j C(s_j, j+1).
+ *
+ * Ownership: the caller allocates and owns every argument buffer.  The library
+ * allocates its own scratch (stream-ordered, released before the call
+ * returns, or at stream completion for GBS_ASYNC calls) and keeps small
+ * per-device tables until the process ends.  Entry points are thread safe.
+ *
+ * Errors: return codes only; nothing aborts or prints.  Arguments are checked
+ * on the host before anything is launched.  Outputs are unspecified when the
+ * call does not return GBS_OK.
+ */
+#ifndef GBS_H
+#define GBS_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define GBS_API __attribute__((visibility("default")))
+#else
+#define GBS_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gbs_status;
+
+enum {
+    GBS_OK = 0,
+    GBS_E_INVALID_ARG = 1,   /* bad size, order, flag bit or null pointer            */
+    GBS_E_NOT_SPD = 2,       /* a pivot of some Q_T was not positive and finite        */
+    GBS_E_OUT_OF_MEMORY = 3, /* scratch allocation failed                              */
+    GBS_E_DEVICE = 4,        /* a HIP runtime call failed                              */
+    GBS_E_UNSUPPORTED = 5    /* valid request that this library does not implement     */
+};
+
+/* flags (bit set) */
+enum {
+    GBS_CLICK = 0,   /* bit 0 clear: click correlators mu and click cumulants kappa~ (default) */
+    GBS_PARITY = 1,  /* bit 0 set:   parity correlators c and cumulants kappa                  */
+    GBS_FP64 = 0,    /* bit 1 clear: every step in FP64 (default)                              */
+    GBS_MIXED = 2,   /* bit 1 set:   FP32 determinant work on a normalised Q, FP64 compensated
+                        inclusion-exclusion and partition sums (not for gbs_cumulant_grad)     */
+    GBS_ASYNC = 4,   /* bit 2 set:   return right after the launches; a NOT_SPD pivot is then
+                        reported only by gbs_last_error after the stream has completed          */
+    GBS_TIMING = 8   /* bit 3 set:   record a HIP event pair around every kernel launch of the
+                        call, on `stream`; read them back with gbs_last_timings               */
+};
+
+/* Kernel stages reported by gbs_last_timings. */
+enum {
+    GBS_STAGE_BUILD_Q = 0,    /* Q = sigma + I/2 (interleaved copy)                 */
+    GBS_STAGE_NORMALISE = 1,  /* per-mode normalisation of Q (GBS_MIXED)            */
+    GBS_STAGE_FORWARD = 2,    /* one order's correlator/cumulant kernel             */
+    GBS_STAGE_ADJOINT = 3,    /* one kernel of the vector-Jacobian product          */
+    GBS_STAGE_BATCHED = 4     /* the persistent batched kernel                      */
+};
+
+typedef struct {
+    int32_t stage;  /* GBS_STAGE_*                                   */
+    int32_t order;  /* subset order of a FORWARD stage, else 0        */
+    float ms;       /* elapsed time between the launch's event pair   */
+} gbs_kernel_time;
+
+#define GBS_MAX_ORDER 5
+#define GBS_MAX_MODES 2048
+
+/* host.  C(M, d) for 0 <= d <= M <= GBS_MAX_MODES; -1 otherwise. */
+GBS_API int64_t gbs_num_subsets(int32_t M, int32_t d);
+
+/* host.  Start of the order-d block: sum_{e=1..d-1} C(M, e); -1 on bad arguments
+ * (1 <= d <= GBS_MAX_ORDER + 1, d <= M + 1). */
+GBS_API int64_t gbs_order_offset(int32_t M, int32_t d);
+
+/* host.  N(M, K) = total number of outputs for orders 1..K; -1 on bad arguments. */
+GBS_API int64_t gbs_total_outputs(int32_t M, int32_t max_order);
+
+/* host.  Colex rank of the d-subset S (host array of d distinct modes in any
+ * order, each in [0, GBS_MAX_MODES)); -1 on bad arguments. */
+GBS_API int64_t gbs_colex_rank(int32_t d, const int32_t* S);
+
+/* host.  Inverse of gbs_colex_rank: writes the d-subset of rank r, ascending,
+ * into the host array S (length d).  GBS_E_INVALID_ARG if d is outside
+ * [1, GBS_MAX_ORDER], r < 0, or the subset would need a mode >= GBS_MAX_MODES. */
+GBS_API gbs_status gbs_colex_unrank(int32_t d, int64_t r, int32_t* S);
+
+/* Correlators only (the cumulant stage is skipped).
+ *   M          number of modes, 1 <= M <= GBS_MAX_MODES
+ *   sigma      device, 2M x 2M FP64 (layout above)
+ *   max_order  K, 1 <= K <= min(GBS_MAX_ORDER, M)
+ *   flags      GBS_CLICK/GBS_PARITY | GBS_FP64/GBS_MIXED | GBS_ASYNC
+ *   corr       device, N(M, K) FP64, overwritten with mu (click) or c (parity)
+ */
+GBS_API gbs_status gbs_correlators(int32_t M, const double* sigma, int32_t max_order, int32_t flags,
+                           double* corr, void* stream);
+
+/* Correlators and cumulants in one pass (the cumulant of each subset is formed
+ * from the correlators of its sub-blocks, computed in the same thread).
+ *   corr   device, N(M, K) FP64, or NULL to skip writing the correlators
+ *   cum    device, N(M, K) FP64, overwritten with kappa~ (click) or kappa (parity)
+ * Other arguments as gbs_correlators. */
+GBS_API gbs_status gbs_cumulants(int32_t M, const double* sigma, int32_t max_order, int32_t flags,
+                         double* corr, double* cum, void* stream);
+
+/* Vector-Jacobian product of gbs_cumulants (FP64 only; GBS_MIXED gives
+ * GBS_E_UNSUPPORTED):
+ *   grad_sigma[i][j] = sum_S grad_corr[S] d corr[S]/d sigma_ij
+ *                    + sum_S grad_cum[S]  d cum[S] /d sigma_ij
+ * with the 4M^2 entries of sigma treated as independent variables, so the
+ * result is symmetric (d log det A = tr(A^{-1} dA), App. D.1 equations).
+ *   grad_corr   device, N(M, K) FP64 upstream gradient of the correlators, or NULL (zero)
+ *   grad_cum    device, N(M, K) FP64 upstream gradient of the cumulants, or NULL (zero)
+ *   grad_sigma  device, 2M x 2M FP64, overwritten (row-major, xxpp)
+ * Work grows like C(M, K) * M^(K-1); intended for K <= 3 at M ~ 100-150.
+ * Deterministic: every sum has a fixed order (no atomics). */
+GBS_API gbs_status gbs_cumulant_grad(int32_t M, const double* sigma, int32_t max_order, int32_t flags,
+                             const double* grad_corr, const double* grad_cum, double* grad_sigma,
+                             void* stream);
+
+/* One covariance instance of a batch. */
+typedef struct {
+    int32_t M;           /* modes of this instance, max_order <= M <= GBS_MAX_MODES           */
+    int32_t reserved;    /* must be 0                                                         */
+    const double* sigma; /* device, 2M x 2M FP64                                              */
+    double* corr;        /* device, N(M, K) FP64, or NULL to skip the correlators             */
+    double* cum;         /* device, N(M, K) FP64 (required)                                   */
+} gbs_instance;
+
+/* Many instances of uneven M in one persistent launch (plus one launch that
+ * forms every instance's Q).  Results equal n separate gbs_cumulants calls
+ * bit for bit in GBS_FP64 mode.  The pipeline is captured once into a HIP
+ * graph per (stream, instance list, order, flags) and replayed on later calls
+ * with the same list; block shape and unroll come from gbs_autotune_batched's
+ * cached choice when one exists for this device, else from a fixed default.
+ *   n      1 <= n <= 4096
+ *   inst   HOST array of n descriptors (pointers inside are device pointers)
+ */
+GBS_API gbs_status gbs_cumulants_batched(int32_t n, const gbs_instance* inst, int32_t max_order,
+                                 int32_t flags, void* stream);
+
+/* Launch shape of the batched kernel. */
+typedef struct {
+    int32_t block;   /* threads per workgroup: 64, 128, 256 or 512          */
+    int32_t unroll;  /* subsets per thread and work item: 1, 2 or 4         */
+    int32_t tile;    /* subsets per work item (multiple of block * unroll)  */
+    int32_t waves_per_cu; /* persistent workgroups per compute unit, 1..8   */
+} gbs_tuning;
+
+/* Times every candidate shape on the given batch (outputs are overwritten,
+ * stream-ordered, synchronising) and caches the fastest for this device,
+ * order and precision; writes it to *best (host) when best is non-NULL. */
+GBS_API gbs_status gbs_autotune_batched(int32_t n, const gbs_instance* inst, int32_t max_order,
+                                int32_t flags, void* stream, gbs_tuning* best);
+
+/* host.  Set (or, with t == NULL, clear) the cached shape used by
+ * gbs_cumulants_batched for this device, order and precision. */
+GBS_API gbs_status gbs_set_tuning(int32_t max_order, int32_t flags, const gbs_tuning* t);
+
+/* host.  After a call returned GBS_E_NOT_SPD (or after a GBS_ASYNC call's
+ * stream completed), the order and colex rank of the first failing subset
+ * seen by this thread's last call; GBS_OK if none.  Either pointer may be NULL. */
+GBS_API gbs_status gbs_last_error(int32_t* order, int64_t* rank);
+
+/* host.  Kernel timings of this thread's last call made with GBS_TIMING: waits
+ * for its events, writes up to `capacity` entries (launch order) to `out` and
+ * returns the number of entries recorded (-1 on a HIP error). */
+GBS_API int32_t gbs_last_timings(int32_t capacity, gbs_kernel_time* out);
+
+/* host.  Static description of a status code. */
+GBS_API const char* gbs_status_string(gbs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBS_H */

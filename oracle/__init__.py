@@ -498,6 +498,8 @@ def _c():
         lib.oracle_forward_sample.restype = i32
         lib.oracle_loss_grad.argtypes = [i32, dp, i32, dp, dp, dp, i32]
         lib.oracle_loss_grad.restype = i32
+        lib.oracle_error_floor.argtypes = [i32, dp, i32, lp, i64, i32, dp, dp, i32]
+        lib.oracle_error_floor.restype = i32
         lib.oracle_threads.argtypes = [i32]
         lib.oracle_threads.restype = i32
         _lib = lib
@@ -549,3 +551,30 @@ def c_loss_grad(sigma: np.ndarray, K: int, target: np.ndarray, threads: int = 0)
     if rc != 0:
         raise RuntimeError(f"oracle_loss_grad failed ({rc})")
     return float(loss[0]), grad
+
+
+# Unit roundoff of FP64 and the multiple of it used in stated tolerances.
+U64 = 2.0 ** -53
+FLOOR_FACTOR = 64.0
+
+
+def c_error_floor(sigma: np.ndarray, d: int, ranks, convention: int = CLICK,
+                  threads: int = 0) -> tuple:
+    """(vmu, vkap): magnitudes of the cancelling terms of each sampled output.
+
+    An FP64 evaluation of mu(S) (or c(S)) sums terms of total magnitude vmu(S),
+    so its rounding error is a small multiple of U64 * vmu(S); vkap(S) carries
+    those errors through the partition sum to first order.  Tolerances are
+    stated as |delta| <= rel * |ref| + FLOOR_FACTOR * U64 * v.
+    """
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    M = sigma.shape[0] // 2
+    ranks = np.ascontiguousarray(ranks, dtype=np.int64)
+    vmu = np.empty(len(ranks))
+    vkap = np.empty(len(ranks))
+    rc = _c().oracle_error_floor(M, _dptr(sigma), d,
+                                 ranks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 len(ranks), convention, _dptr(vmu), _dptr(vkap), threads)
+    if rc != 0:
+        raise RuntimeError(f"oracle_error_floor failed ({rc})")
+    return vmu, vkap

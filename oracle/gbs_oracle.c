@@ -364,3 +364,57 @@ done:
     free(Q); free(p); free(mu); free(kap); free(mubar); free(pbar);
     return err;
 }
+
+/*
+ * Magnitudes of the cancelling terms, for stating tolerances:
+ *   vmu(S)  = sum_{T subset S} w_T p(T), w_T = 1 (click) or 2^|T| (parity):
+ *             FP64 evaluation of the correlator errs by O(u) * vmu(S);
+ *   vkap(S) = sum_pi |w(pi)| sum_{B in pi} vmu(B) prod_{B' in pi, B' != B} |m(B')|:
+ *             the first-order propagation of those errors into the cumulant.
+ */
+int oracle_error_floor(int M, const double* sigma, int d, const int64_t* ranks, int64_t n,
+                       int convention, double* vmu, double* vkap, int threads) {
+    if (M < 1 || d < 1 || d > KMAX || d > M) return 1;
+    init_parts();
+    oracle_threads(threads);
+    double* Q = make_q(sigma, M);
+    if (!Q) return 3;
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(| : err)
+    for (int64_t i = 0; i < n; ++i) {
+        int S[KMAX];
+        unrank(d, ranks[i], S);
+        double p[1 << KMAX], m[1 << KMAX], v[1 << KMAX];
+        int full = (1 << d) - 1;
+        for (unsigned T = 0; T <= (unsigned)full; ++T) err |= vacuum_prob(Q, M, S, d, T, &p[T]);
+        for (unsigned B = 1; B <= (unsigned)full; ++B) {
+            nsum acc = {0.0, 0.0};
+            double mag = 0.0;
+            for (unsigned T = 0; T <= B; ++T) {
+                if ((T & B) != T) continue;
+                int t = popc(T);
+                double w = convention == 0 ? 1.0 : ldexp(1.0, t);
+                nadd(&acc, (t % 2 ? -w : w) * p[T]);
+                mag += w * p[T];
+            }
+            m[B] = nval(&acc);
+            v[B] = mag;
+        }
+        const partitions* P = &g_parts[d];
+        double vk = 0.0;
+        for (int j = 0; j < P->n; ++j) {
+            int nb = P->nblocks[j];
+            double w = fabs(weight(nb));
+            for (int b = 0; b < nb; ++b) {
+                double prod = w * v[P->blocks[j][b]];
+                for (int b2 = 0; b2 < nb; ++b2)
+                    if (b2 != b) prod *= fabs(m[P->blocks[j][b2]]);
+                vk += prod;
+            }
+        }
+        vmu[i] = v[full];
+        vkap[i] = vk;
+    }
+    free(Q);
+    return err;
+}

@@ -1,0 +1,268 @@
+"""ctypes binding of libgbs (include/gbs.h): the same entry points under the same
+names, argument marshalling only.  Device buffers are torch tensors; every
+compute step runs in the library's HIP kernels.  There is no fallback: if
+libgbs.so has not been built, loading raises."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgbs.so")
+
+GBS_OK = 0
+GBS_E_INVALID_ARG = 1
+GBS_E_NOT_SPD = 2
+GBS_E_OUT_OF_MEMORY = 3
+GBS_E_DEVICE = 4
+GBS_E_UNSUPPORTED = 5
+
+GBS_CLICK = 0
+GBS_PARITY = 1
+GBS_FP64 = 0
+GBS_MIXED = 2
+GBS_ASYNC = 4
+GBS_TIMING = 8
+
+GBS_STAGE_BUILD_Q = 0
+GBS_STAGE_NORMALISE = 1
+GBS_STAGE_FORWARD = 2
+GBS_STAGE_ADJOINT = 3
+GBS_STAGE_BATCHED = 4
+STAGE_NAMES = {0: "build_q", 1: "normalise", 2: "forward", 3: "adjoint", 4: "batched"}
+
+GBS_MAX_ORDER = 5
+GBS_MAX_MODES = 2048
+
+# every symbol declared in include/gbs.h
+EXPORTS = (
+    "gbs_num_subsets", "gbs_order_offset", "gbs_total_outputs", "gbs_colex_rank",
+    "gbs_colex_unrank", "gbs_correlators", "gbs_cumulants", "gbs_cumulant_grad",
+    "gbs_cumulants_batched", "gbs_autotune_batched", "gbs_set_tuning", "gbs_last_error",
+    "gbs_last_timings", "gbs_status_string",
+)
+
+
+class GBSError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {gbs_status_string(status)} (status {status})")
+
+
+class gbs_instance(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sigma", ctypes.c_void_p), ("corr", ctypes.c_void_p), ("cum", ctypes.c_void_p)]
+
+
+class gbs_tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("unroll", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class gbs_kernel_time(ctypes.Structure):
+    _fields_ = [("stage", ctypes.c_int32), ("order", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgbs.so (raises if it is missing: there is no other implementation)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2511_14923_amd/build.py` "
+                          "or __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    L.gbs_num_subsets.argtypes = [i32, i32]
+    L.gbs_num_subsets.restype = i64
+    L.gbs_order_offset.argtypes = [i32, i32]
+    L.gbs_order_offset.restype = i64
+    L.gbs_total_outputs.argtypes = [i32, i32]
+    L.gbs_total_outputs.restype = i64
+    L.gbs_colex_rank.argtypes = [i32, ctypes.POINTER(i32)]
+    L.gbs_colex_rank.restype = i64
+    L.gbs_colex_unrank.argtypes = [i32, i64, ctypes.POINTER(i32)]
+    L.gbs_colex_unrank.restype = i32
+    L.gbs_correlators.argtypes = [i32, vp, i32, i32, vp, vp]
+    L.gbs_correlators.restype = i32
+    L.gbs_cumulants.argtypes = [i32, vp, i32, i32, vp, vp, vp]
+    L.gbs_cumulants.restype = i32
+    L.gbs_cumulant_grad.argtypes = [i32, vp, i32, i32, vp, vp, vp, vp]
+    L.gbs_cumulant_grad.restype = i32
+    L.gbs_cumulants_batched.argtypes = [i32, ctypes.POINTER(gbs_instance), i32, i32, vp]
+    L.gbs_cumulants_batched.restype = i32
+    L.gbs_autotune_batched.argtypes = [i32, ctypes.POINTER(gbs_instance), i32, i32, vp,
+                                       ctypes.POINTER(gbs_tuning)]
+    L.gbs_autotune_batched.restype = i32
+    L.gbs_set_tuning.argtypes = [i32, i32, ctypes.POINTER(gbs_tuning)]
+    L.gbs_set_tuning.restype = i32
+    L.gbs_last_error.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    L.gbs_last_error.restype = i32
+    L.gbs_last_timings.argtypes = [i32, ctypes.POINTER(gbs_kernel_time)]
+    L.gbs_last_timings.restype = i32
+    L.gbs_status_string.argtypes = [i32]
+    L.gbs_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != GBS_OK:
+        raise GBSError(status, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    if t.dtype != torch.float64:
+        raise ValueError("float64 tensor required")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor required")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream, device):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+# ---- host helpers -----------------------------------------------------------
+
+def gbs_num_subsets(M: int, d: int) -> int:
+    return int(lib().gbs_num_subsets(M, d))
+
+
+def gbs_order_offset(M: int, d: int) -> int:
+    return int(lib().gbs_order_offset(M, d))
+
+
+def gbs_total_outputs(M: int, max_order: int) -> int:
+    return int(lib().gbs_total_outputs(M, max_order))
+
+
+def gbs_colex_rank(S) -> int:
+    arr = (ctypes.c_int32 * len(S))(*[int(x) for x in S])
+    return int(lib().gbs_colex_rank(len(S), arr))
+
+
+def gbs_colex_unrank(d: int, r: int) -> tuple:
+    arr = (ctypes.c_int32 * max(d, 1))()
+    _check(lib().gbs_colex_unrank(d, r, arr), "gbs_colex_unrank")
+    return tuple(arr[:d])
+
+
+def gbs_last_error() -> tuple:
+    o, r = ctypes.c_int32(), ctypes.c_int64()
+    st = lib().gbs_last_error(ctypes.byref(o), ctypes.byref(r))
+    return st, o.value, r.value
+
+
+def gbs_last_timings(capacity: int = 64) -> list:
+    """[(stage name, order, ms), ...] of this thread's last GBS_TIMING call."""
+    buf = (gbs_kernel_time * capacity)()
+    n = int(lib().gbs_last_timings(capacity, buf))
+    if n < 0:
+        raise GBSError(GBS_E_DEVICE, "gbs_last_timings")
+    return [(STAGE_NAMES.get(buf[i].stage, str(buf[i].stage)), buf[i].order, float(buf[i].ms))
+            for i in range(min(n, capacity))]
+
+
+def gbs_status_string(status: int) -> str:
+    return lib().gbs_status_string(status).decode()
+
+
+# ---- device entry points ----------------------------------------------------
+
+def _out(buf, n, like):
+    if buf is None:
+        return torch.empty(n, dtype=torch.float64, device=like.device)
+    return buf
+
+
+def gbs_correlators(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0, corr=None,
+                    stream=None) -> torch.Tensor:
+    n = gbs_total_outputs(M, max_order)
+    corr = _out(corr, max(n, 0), sigma)
+    with torch.cuda.device(sigma.device):
+        st = lib().gbs_correlators(M, _ptr(sigma), max_order, flags, _ptr(corr),
+                                   _stream(stream, sigma.device))
+    _check(st, "gbs_correlators")
+    return corr
+
+
+def gbs_cumulants(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0, corr=None, cum=None,
+                  stream=None, want_corr: bool = True) -> tuple:
+    n = gbs_total_outputs(M, max_order)
+    if want_corr:
+        corr = _out(corr, max(n, 0), sigma)
+    cum = _out(cum, max(n, 0), sigma)
+    with torch.cuda.device(sigma.device):
+        st = lib().gbs_cumulants(M, _ptr(sigma), max_order, flags, _ptr(corr), _ptr(cum),
+                                 _stream(stream, sigma.device))
+    _check(st, "gbs_cumulants")
+    return corr, cum
+
+
+def gbs_cumulant_grad(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0,
+                      grad_corr=None, grad_cum=None, grad_sigma=None, stream=None) -> torch.Tensor:
+    if grad_sigma is None:
+        grad_sigma = torch.empty_like(sigma)
+    with torch.cuda.device(sigma.device):
+        st = lib().gbs_cumulant_grad(M, _ptr(sigma), max_order, flags, _ptr(grad_corr),
+                                     _ptr(grad_cum), _ptr(grad_sigma), _stream(stream, sigma.device))
+    _check(st, "gbs_cumulant_grad")
+    return grad_sigma
+
+
+def _instances(instances):
+    arr = (gbs_instance * len(instances))()
+    for i, (M, sigma, corr, cum) in enumerate(instances):
+        arr[i].M = M
+        arr[i].reserved = 0
+        arr[i].sigma = _ptr(sigma).value
+        arr[i].corr = _ptr(corr).value if corr is not None else None
+        arr[i].cum = _ptr(cum).value
+    return arr
+
+
+def gbs_cumulants_batched(instances, max_order: int, flags: int = 0, stream=None) -> None:
+    """instances: list of (M, sigma, corr or None, cum) with device tensors."""
+    arr = _instances(instances)
+    dev = instances[0][1].device
+    with torch.cuda.device(dev):
+        st = lib().gbs_cumulants_batched(len(instances), arr, max_order, flags, _stream(stream, dev))
+    _check(st, "gbs_cumulants_batched")
+
+
+def gbs_autotune_batched(instances, max_order: int, flags: int = 0, stream=None) -> dict:
+    arr = _instances(instances)
+    dev = instances[0][1].device
+    best = gbs_tuning()
+    with torch.cuda.device(dev):
+        st = lib().gbs_autotune_batched(len(instances), arr, max_order, flags, _stream(stream, dev),
+                                        ctypes.byref(best))
+    _check(st, "gbs_autotune_batched")
+    return best.as_dict()
+
+
+def gbs_set_tuning(max_order: int, flags: int, tuning: dict | None) -> None:
+    if tuning is None:
+        _check(lib().gbs_set_tuning(max_order, flags, None), "gbs_set_tuning")
+        return
+    t = gbs_tuning(**tuning)
+    _check(lib().gbs_set_tuning(max_order, flags, ctypes.byref(t)), "gbs_set_tuning")

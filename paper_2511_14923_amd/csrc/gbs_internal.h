@@ -1,0 +1,51 @@
+// Internal host-side interface between the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gbs_device.h"
+
+namespace gbs {
+
+// Binomial table C(n, k), k = 0..kMaxOrder+1, n = 0..GBS_MAX_MODES, laid out
+// [k][n] with leading dimension kBinLd.
+constexpr int kBinLd = GBS_MAX_MODES + 1;
+constexpr int kBinRows = kMaxOrder + 2;
+
+uint64_t host_binom(int n, int k);
+
+// Per-device state created once per device and kept until the process ends.
+struct DeviceContext {
+  int device = -1;
+  uint64_t* binom = nullptr;  // device copy of the binomial table
+  int cu_count = 0;
+};
+
+// Context of the current device (created on first use); nullptr on failure.
+DeviceContext* current_context(hipError_t* err);
+
+// Q = sigma + I/2 in interleaved (x_0 p_0 x_1 p_1 ...) order, full symmetric
+// 2M x 2M FP64, built from sigma's lower triangle.
+hipError_t launch_build_q(const double* sigma, int M, double* Qi, hipStream_t s);
+
+// Mixed-precision operands: per-mode block Cholesky factors of Q, the
+// single-mode vacuum probabilities pk (FP64) and the normalised off-diagonal
+// blocks E = L_k^{-1} Q_kl L_l^{-T} (FP32, interleaved 2M x 2M, zero diagonal blocks).
+hipError_t launch_build_normalised(const double* Qi, int M, double* pk, float* E, hipStream_t s);
+
+// Optional per-launch event timing (GBS_TIMING), per calling thread.
+void timing_start_call(bool enabled);
+hipError_t timing_begin(hipStream_t s, int stage, int order);
+hipError_t timing_end(hipStream_t s);
+
+// Reset a status word (fill kernel, safe inside graph capture).
+hipError_t launch_clear_status(DeviceStatus* st, hipStream_t s);
+
+// Order-d forward pass over all C(M, d) subsets.
+// FP64 reads Qi; MIXED reads pk and E.  corr and/or cum may be null (not written).
+hipError_t launch_forward(int d, int M, int flags, const double* Qi, const double* pk,
+                          const float* E, const uint64_t* binom, double* corr, double* cum,
+                          DeviceStatus* st, hipStream_t s);
+
+}  // namespace gbs

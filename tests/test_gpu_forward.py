@@ -1,0 +1,222 @@
+"""GPU parity of the forward path (gbs_correlators / gbs_cumulants) against the
+CPU oracle, element by element, through the C ABI."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gbs_inputs as G
+import oracle as O
+from parity import assert_within, fp64_tolerance, rel_stats
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_2511_14923_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    P.lib()
+    return P
+
+
+def _run(P, sigma, K, flags=0, want_corr=True):
+    import torch
+    M = sigma.shape[0] // 2
+    s = torch.from_numpy(np.ascontiguousarray(sigma)).to("cuda:0")
+    corr, cum = P.gbs_cumulants(M, s, K, flags, want_corr=want_corr)
+    torch.cuda.synchronize()
+    return (corr.cpu().numpy() if corr is not None else None), cum.cpu().numpy()
+
+
+def _check_full(P, sigma, K, conv, flags_extra=0, what=""):
+    M = sigma.shape[0] // 2
+    corr, cum = _run(P, sigma, K, conv | flags_extra)
+    rc, rk = O.c_forward(sigma, K, conv)
+    for d in range(1, K + 1):
+        a, b = O.order_offset(M, d), O.order_offset(M, d + 1)
+        ranks = np.arange(b - a, dtype=np.int64)
+        vmu, vkap = O.c_error_floor(sigma, d, ranks, conv)
+        assert_within(corr[a:b], rc[a:b], fp64_tolerance(rc[a:b], vmu), f"{what} corr d={d}")
+        assert_within(cum[a:b], rk[a:b], fp64_tolerance(rk[a:b], vkap), f"{what} cum d={d}")
+    return corr, cum
+
+
+@pytest.mark.parametrize("conv", [0, 1], ids=["click", "parity"])
+def test_m16_k3_against_golden(P, conv):
+    _say("case: M=16 K=3 full", conv)
+    tag = "click" if conv == 0 else "parity"
+    g = np.load(os.path.join(HERE, "golden", f"m16_k3_{tag}.npz"))
+    corr, cum = _run(P, g["sigma"], 3, conv)
+    for d in (1, 2, 3):
+        a, b = O.order_offset(16, d), O.order_offset(16, d + 1)
+        vmu, vkap = O.c_error_floor(g["sigma"], d, np.arange(b - a, dtype=np.int64), conv)
+        assert_within(corr[a:b], g["corr"][a:b], fp64_tolerance(g["corr"][a:b], vmu), f"corr d={d}")
+        assert_within(cum[a:b], g["cum"][a:b], fp64_tolerance(g["cum"][a:b], vkap), f"cum d={d}")
+
+
+@pytest.mark.parametrize("conv", [0, 1], ids=["click", "parity"])
+def test_m40_k5_full(P, conv):
+    """658,008 order-5 subsets: thousands of workgroups and a ragged last one."""
+    _say("case: M=40 K=5 full", conv)
+    inst = G.make_instance("m144_k5", M=40, seed=17)
+    _check_full(P, inst.sigma, 5, conv, what="M=40")
+
+
+def test_m100_k4_full(P):
+    """The M = 100, K = 4 workload, every output."""
+    _say("case: M=100 K=4 full")
+    inst = G.make_instance("m100_k4")
+    corr, cum = _check_full(P, inst.sigma, 4, 0, what="M=100")
+    a = O.order_offset(100, 4)
+    rc, _ = O.c_forward_sample(inst.sigma, 4, np.arange(0, 50, dtype=np.int64))
+    _say("rel stats order 4 corr", rel_stats(corr[a:a + 50], rc))
+
+
+def test_m144_k5_sampled(P):
+    """The M = 144, K = 5 workload in the launch configuration the benchmark
+    times; every order-1..3 output and 20,000 sampled outputs of orders 4 and 5."""
+    _say("case: M=144 K=5 sampled")
+    inst = G.make_instance("m144_k5")
+    corr, cum = _run(P, inst.sigma, 5)
+    for d in range(1, 6):
+        n = math.comb(144, d)
+        ranks = np.arange(n, dtype=np.int64) if d <= 3 else G.random_ranks(n, 20000, seed=100 + d)
+        rc, rk = O.c_forward_sample(inst.sigma, d, ranks)
+        vmu, vkap = O.c_error_floor(inst.sigma, d, ranks)
+        off = O.order_offset(144, d)
+        assert_within(corr[off + ranks], rc, fp64_tolerance(rc, vmu), f"M=144 corr d={d}")
+        assert_within(cum[off + ranks], rk, fp64_tolerance(rk, vkap), f"M=144 cum d={d}")
+        if d == 5:
+            _say("order 5 corr rel", rel_stats(corr[off + ranks], rc))
+            _say("order 5 cum |delta|/vkap max",
+                 float(np.max(np.abs(cum[off + ranks] - rk) / vkap)))
+    # the last outputs of the layout (ragged tail of the order-5 launch)
+    tail = np.arange(math.comb(144, 5) - 300, math.comb(144, 5), dtype=np.int64)
+    rc, rk = O.c_forward_sample(inst.sigma, 5, tail)
+    vmu, vkap = O.c_error_floor(inst.sigma, 5, tail)
+    off = O.order_offset(144, 5)
+    assert_within(corr[off + tail], rc, fp64_tolerance(rc, vmu), "tail corr")
+    assert_within(cum[off + tail], rk, fp64_tolerance(rk, vkap), "tail cum")
+
+
+def test_python_oracle_direct(P):
+    """Same check against the Python tier of the oracle (fsum, library Cholesky)."""
+    _say("case: M=9 K=5 python oracle")
+    inst = G.make_instance("m144_k5", M=9, seed=23)
+    for conv in (0, 1):
+        corr, cum = _run(P, inst.sigma, 5, conv)
+        rc, rk = O.correlators_and_cumulants(inst.sigma, 5, conv)
+        assert np.allclose(corr, rc, rtol=1e-10, atol=1e-14)
+        assert np.allclose(cum, rk, rtol=1e-8, atol=1e-13)
+
+
+@pytest.mark.parametrize("M,K", [(1, 1), (2, 2), (5, 5), (6, 5), (17, 3), (257, 2)])
+def test_small_and_ragged_sizes(P, M, K):
+    _say("case: sizes", M, K)
+    inst = G.make_instance("m144_k5", M=M, seed=M)
+    _check_full(P, inst.sigma, K, 0, what=f"M={M}")
+
+
+def test_max_modes(P):
+    """M = GBS_MAX_MODES (the binomial table is then read from global memory)."""
+    _say("case: M=2048 K=2")
+    M = 2048
+    rng = np.random.default_rng(1)
+    # product of independent lossy squeezed modes plus weak random couplings
+    r = rng.uniform(0.3, 1.0, M)
+    eta = rng.uniform(0.3, 0.6, M)
+    sigma = G.product_state_covariance(r, eta)
+    B = rng.standard_normal((2 * M, 2 * M)) * 5e-4  # spectral norm ~0.06: Q stays SPD
+    sigma = sigma + 0.5 * (B + B.T)
+    corr, cum = _run(P, sigma, 2)
+    for d in (1, 2):
+        n = math.comb(M, d)
+        ranks = G.random_ranks(n, 5000, seed=d)
+        rc, rk = O.c_forward_sample(sigma, d, ranks)
+        vmu, vkap = O.c_error_floor(sigma, d, ranks)
+        off = O.order_offset(M, d)
+        assert_within(corr[off + ranks], rc, fp64_tolerance(rc, vmu), f"max corr d={d}")
+        assert_within(cum[off + ranks], rk, fp64_tolerance(rk, vkap), f"max cum d={d}")
+
+
+def test_vacuum_and_product_state(P):
+    _say("case: vacuum / product")
+    corr, cum = _run(P, G.vacuum_covariance(8), 4)
+    assert np.all(corr == 0.0) and np.all(np.abs(cum) < 1e-15)
+    c, k = _run(P, G.vacuum_covariance(8), 4, 1)
+    assert np.allclose(c, 1.0, atol=1e-15) and np.allclose(k[:8], 1.0, atol=1e-15)
+    rng = np.random.default_rng(2)
+    r, eta = rng.uniform(0.3, 1.3, 9), rng.uniform(0.2, 0.9, 9)
+    corr, cum = _run(P, G.product_state_covariance(r, eta), 5)
+    assert np.all(np.abs(cum[9:]) < 1e-14)
+    pos = 0
+    for d in range(1, 6):
+        for S in O.subsets_colex(9, d):
+            # inclusion-exclusion of 2^d terms of size <= 1: rounding floor ~1e-14
+            assert corr[pos] == pytest.approx(np.prod(corr[list(S)]), rel=1e-10, abs=1e-14)
+            pos += 1
+
+
+def test_correlators_only_and_corr_null(P):
+    import torch
+    _say("case: correlators-only / corr NULL")
+    inst = G.make_instance("m144_k5", M=30, seed=3)
+    s = torch.from_numpy(inst.sigma).to("cuda:0")
+    corr_only = P.gbs_correlators(30, s, 4).cpu().numpy()
+    corr, cum = _run(P, inst.sigma, 4)
+    _, cum2 = _run(P, inst.sigma, 4, want_corr=False)
+    assert np.array_equal(corr_only, corr)
+    assert np.array_equal(cum2, cum)
+
+
+def test_deterministic(P):
+    _say("case: determinism")
+    inst = G.make_instance("m144_k5", M=60, seed=5)
+    a = _run(P, inst.sigma, 5)
+    b = _run(P, inst.sigma, 5)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_not_spd_reported(P):
+    """A covariance with a non-physical block: the kernels' own pivot checks turn
+    it into GBS_E_NOT_SPD and gbs_last_error names a failing subset."""
+    import torch
+    _say("case: not SPD")
+    M = 6
+    sigma = G.vacuum_covariance(M)
+    sigma[2, 2] = sigma[2 + M, 2 + M] = -0.9  # mode 2: Q_22 has negative pivots
+    s = torch.from_numpy(sigma).to("cuda:0")
+    with pytest.raises(P.GBSError) as ei:
+        P.gbs_cumulants(M, s, 3)
+    assert ei.value.status == P.GBS_E_NOT_SPD
+    st, order, rank = P.gbs_last_error()
+    assert st == P.GBS_E_NOT_SPD and 1 <= order <= 3
+    assert 2 in P.gbs_colex_unrank(order, rank)
+    # a good call clears it
+    P.gbs_cumulants(M, torch.from_numpy(G.vacuum_covariance(M)).to("cuda:0"), 3)
+    assert P.gbs_last_error()[0] == P.GBS_OK
+
+
+def test_async_and_side_stream(P):
+    import torch
+    _say("case: async / side stream")
+    inst = G.make_instance("m144_k5", M=25, seed=9)
+    s = torch.from_numpy(inst.sigma).to("cuda:0")
+    ref = _run(P, inst.sigma, 4)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        corr, cum = P.gbs_cumulants(25, s, 4, P.GBS_ASYNC, stream=stream)
+    stream.synchronize()
+    assert P.gbs_last_error()[0] == P.GBS_OK
+    assert np.array_equal(corr.cpu().numpy(), ref[0]) and np.array_equal(cum.cpu().numpy(), ref[1])
