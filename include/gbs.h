@@ -170,7 +170,7 @@ GBS_API gbs_status gbs_cumulants_batched(int32_t n, const gbs_instance* inst, in
 
 /* Launch shape of the batched kernel. */
 typedef struct {
-    int32_t block;   /* threads per workgroup: 64, 128, 256 or 512          */
+    int32_t block;   /* threads per workgroup: 64, 128 or 256               */
     int32_t unroll;  /* subsets per thread and work item: 1, 2 or 4         */
     int32_t tile;    /* subsets per work item (multiple of block * unroll)  */
     int32_t waves_per_cu; /* persistent workgroups per compute unit, 1..8   */

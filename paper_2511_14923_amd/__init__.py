@@ -15,3 +15,5 @@ from ._binding import (  # noqa: F401
 )
 
 __all__ = [n for n in dir() if n.startswith("gbs_") or n.startswith("GBS")] + ["lib", "EXPORTS", "STAGE_NAMES"]
+from .autograd import (GBSCumulants, cumulant_matching_loss, cumulants,  # noqa: E402,F401
+                       interferometer_symplectic, lossy_squeezed_covariance)

@@ -1,0 +1,459 @@
+// Adjoint (vector-Jacobian product) of the correlator/cumulant path.
+//
+// Forward chain, for all subsets up to order K (m = mu for click, c for parity):
+//   p(T) = det(Q_T)^(-1/2)                                   (App. D.1)
+//   m(B) = sum_{T subset B} a(B,T) p(T),  a = (-1)^|T| (click) or (-1)^|B| (-2)^|T| (parity)
+//   k(S) = sum_{pi partition of S} w(pi) prod_{B in pi} m(B) (Eq. cumulant_corr_main)
+// Reverse, given the upstream gradients gm(S) (correlators) and gk(S) (cumulants):
+//   mbar(B) = gm(B) + gk(B) + sum_{X disjoint from B, 1 <= |X| <= K-|B|} gk(B + X) D1(X),
+//      where d k(S)/d m(B) = D1(S \ B) and, for X non-empty,
+//      D1(X) = sum_{pi partition of X} (-1)^|pi| |pi|! prod_{B' in pi} m(B')
+//      (the partitions of S having B as a block are pi' + {B}, pi' a partition of
+//      S \ B, with weight w(|pi'| + 1) = (-1)^|pi'| |pi'|!);
+//   pbar(T) = sum_{B superset of T, |B| <= K} a(B,T) mbar(B);
+//   d p(T) / d Q_T = -p(T) Q_T^{-1} / 2   (d log det A = tr(A^{-1} dA)),
+//   so the 2x2 block (i, j) of dL/dsigma is
+//      G_ij = sum_{T containing i and j} -pbar(T) p(T) [Q_T^{-1}]_{ij} / 2.
+// Every sum is a gather owned by one wavefront (the superset sums by their
+// target subset, G_ij by its mode pair) reduced in a fixed order: no atomics,
+// results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "gbs_internal.h"
+
+namespace gbs {
+
+namespace {
+
+constexpr int kWave = 64;
+
+// Set partitions of {0..n-1}, n <= 4, as block masks (restricted growth strings).
+struct PartTable {
+  int count[5];
+  int nblocks[5][15];
+  unsigned char blocks[5][15][4];
+};
+
+constexpr PartTable make_partitions() {
+  PartTable t{};
+  for (int n = 1; n <= 4; ++n) {
+    int lab[4] = {0, 0, 0, 0};
+    int total = 1;
+    for (int i = 0; i < n; ++i) total *= n;
+    int cnt = 0;
+    for (int code = 0; code < total; ++code) {
+      int c = code;
+      for (int i = 0; i < n; ++i) {
+        lab[i] = c % n;
+        c /= n;
+      }
+      // restricted growth: lab[0] = 0, lab[i] <= 1 + max(lab[0..i-1])
+      bool ok = lab[0] == 0;
+      int mx = 0;
+      for (int i = 1; i < n && ok; ++i) {
+        if (lab[i] > mx + 1) ok = false;
+        if (lab[i] > mx) mx = lab[i];
+      }
+      if (!ok) continue;
+      t.nblocks[n][cnt] = mx + 1;
+      for (int b = 0; b < 4; ++b) t.blocks[n][cnt][b] = 0;
+      for (int i = 0; i < n; ++i) t.blocks[n][cnt][lab[i]] |= (unsigned char)(1u << i);
+      ++cnt;
+    }
+    t.count[n] = cnt;
+  }
+  return t;
+}
+
+__constant__ PartTable kParts = make_partitions();
+
+__device__ __forceinline__ uint64_t binom_at(const uint64_t* __restrict__ bin, int n, int k) {
+  return bin[k * kBinLd + n];
+}
+
+__device__ __forceinline__ uint64_t rank_sorted(const uint64_t* __restrict__ bin, const int* s,
+                                                int n) {
+  uint64_t r = 0;
+  for (int j = 0; j < n; ++j) r += binom_at(bin, s[j], j + 1);
+  return r;
+}
+
+// j-subset of [0, universe) with colex rank r, ascending.
+__device__ __forceinline__ void unrank_dyn(const uint64_t* __restrict__ bin, uint64_t r, int j,
+                                           int universe, int* x) {
+  int hi = universe;
+  for (int t = j - 1; t >= 0; --t) {
+    int lo = t, h = hi - 1;
+    while (lo < h) {
+      const int mid = (lo + h + 1) >> 1;
+      if (binom_at(bin, mid, t + 1) <= r) lo = mid; else h = mid - 1;
+    }
+    x[t] = lo;
+    r -= binom_at(bin, lo, t + 1);
+    hi = lo;
+  }
+}
+
+// Modes of a j-subset of the complement of B (sorted, size k): complement
+// index -> mode, skipping B's elements in increasing order.
+__device__ __forceinline__ void complement_modes(const int* xc, int j, const int* B, int k, int* x) {
+  for (int t = 0; t < j; ++t) {
+    int m = xc[t];
+    for (int i = 0; i < k; ++i)
+      if (B[i] <= m) ++m;
+    x[t] = m;
+  }
+}
+
+// Sorted union of two sorted disjoint sets.
+__device__ __forceinline__ int merge_sorted(const int* a, int na, const int* b, int nb, int* out) {
+  int i = 0, j = 0, n = 0;
+  while (i < na || j < nb) {
+    if (j >= nb || (i < na && a[i] < b[j])) out[n++] = a[i++];
+    else out[n++] = b[j++];
+  }
+  return n;
+}
+
+// Flat index over all X of sizes jmin..jmax within a universe of u modes.
+__device__ __forceinline__ void flat_to_sized(const uint64_t* __restrict__ bin, uint64_t i, int jmin,
+                                              int jmax, int u, int* j, uint64_t* r) {
+  for (int t = jmin; t <= jmax; ++t) {
+    const uint64_t c = binom_at(bin, u, t);
+    if (i < c) {
+      *j = t;
+      *r = i;
+      return;
+    }
+    i -= c;
+  }
+  *j = -1;
+  *r = 0;
+}
+
+__device__ __forceinline__ uint64_t count_sized(const uint64_t* __restrict__ bin, int jmin, int jmax,
+                                                int u) {
+  uint64_t c = 0;
+  for (int t = jmin; t <= jmax; ++t) c += binom_at(bin, u, t);
+  return c;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+struct Offsets {
+  int64_t off[kMaxOrder + 2];  // start of order-d block, off[1] = 0
+};
+
+// ---------------------------------------------------------------------------
+// D1(X) for every non-empty X with |X| <= K - 1 (one thread per X).
+__global__ void d1_kernel(const double* __restrict__ m, int M, int K, Offsets o,
+                          const uint64_t* __restrict__ bin, double* __restrict__ d1) {
+  const int64_t total = o.off[K];  // orders 1..K-1
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int j = 1;
+    while (idx >= o.off[j + 1]) ++j;
+    const uint64_t r = (uint64_t)(idx - o.off[j]);
+    int x[kMaxOrder];
+    unrank_dyn(bin, r, j, M, x);
+    double mv[16];
+    mv[0] = 1.0;
+    for (unsigned mask = 1; mask < (1u << j); ++mask) {
+      int sub[kMaxOrder], n = 0;
+      for (int t = 0; t < j; ++t)
+        if (mask & (1u << t)) sub[n++] = x[t];
+      mv[mask] = m[o.off[n] + rank_sorted(bin, sub, n)];
+    }
+    double acc = 0.0;
+    for (int q = 0; q < kParts.count[j]; ++q) {
+      const int nb = kParts.nblocks[j][q];
+      double w = (nb & 1) ? -1.0 : 1.0;
+      for (int f = 2; f <= nb; ++f) w *= f;  // (-1)^nb nb!
+      for (int b = 0; b < nb; ++b) w *= mv[kParts.blocks[j][q][b]];
+      acc += w;
+    }
+    d1[idx] = acc;
+  }
+}
+
+// mbar(B) for every B of order k (one wavefront per B).
+__global__ __launch_bounds__(kWave) void mbar_kernel(int M, int K, int k, Offsets o,
+                                                     const uint64_t* __restrict__ bin,
+                                                     const double* __restrict__ gm,
+                                                     const double* __restrict__ gk,
+                                                     const double* __restrict__ d1,
+                                                     double* __restrict__ mbar) {
+  const uint64_t rb = blockIdx.x;
+  const int lane = threadIdx.x;
+  int B[kMaxOrder];
+  unrank_dyn(bin, rb, k, M, B);
+  double acc = 0.0;
+  if (gk && k < K) {
+    const int u = M - k;
+    const uint64_t nx = count_sized(bin, 1, K - k, u);
+    for (uint64_t i = lane; i < nx; i += kWave) {
+      int j;
+      uint64_t rx;
+      flat_to_sized(bin, i, 1, K - k, u, &j, &rx);
+      int xc[kMaxOrder], X[kMaxOrder], U[kMaxOrder];
+      unrank_dyn(bin, rx, j, u, xc);
+      complement_modes(xc, j, B, k, X);
+      const int n = merge_sorted(B, k, X, j, U);
+      acc = fma(gk[o.off[n] + rank_sorted(bin, U, n)], d1[o.off[j] + rank_sorted(bin, X, j)], acc);
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const int64_t at = o.off[k] + (int64_t)rb;
+    double v = acc;
+    if (gk) v += gk[at];
+    if (gm) v += gm[at];
+    mbar[at] = v;
+  }
+}
+
+// pbar(T) for every T of order t (one wavefront per T).
+__global__ __launch_bounds__(kWave) void pbar_kernel(int M, int K, int t, int parity, Offsets o,
+                                                     const uint64_t* __restrict__ bin,
+                                                     const double* __restrict__ mbar,
+                                                     double* __restrict__ pbar) {
+  const uint64_t rt = blockIdx.x;
+  const int lane = threadIdx.x;
+  int T[kMaxOrder];
+  unrank_dyn(bin, rt, t, M, T);
+  const int u = M - t;
+  const uint64_t nx = count_sized(bin, 0, K - t, u);
+  double acc = 0.0;
+  for (uint64_t i = lane; i < nx; i += kWave) {
+    int j;
+    uint64_t rx;
+    flat_to_sized(bin, i, 0, K - t, u, &j, &rx);
+    int xc[kMaxOrder], X[kMaxOrder], U[kMaxOrder];
+    unrank_dyn(bin, rx, j, u, xc);
+    complement_modes(xc, j, T, t, X);
+    const int n = merge_sorted(T, t, X, j, U);
+    const double v = mbar[o.off[n] + rank_sorted(bin, U, n)];
+    acc += (parity && (n & 1)) ? -v : v;
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    // click: (-1)^t;  parity: (-2)^t (the (-1)^|B| factor is inside the sum)
+    double coef = (t & 1) ? -1.0 : 1.0;
+    if (parity) coef *= (double)(1 << t);
+    pbar[o.off[t] + (int64_t)rt] = coef * acc;
+  }
+}
+
+// Trailing (base) block of Q_T^{-1}: the first NX blocks of `modes` are
+// eliminated, the last NB (1 or 2) are the base modes.
+template <int NX, int NB>
+__device__ __forceinline__ void base_inverse(const double* __restrict__ Qi, int M, const int* modes,
+                                             double (&G)[4], bool& bad) {
+  constexpr int N = NX + NB;
+  Tri<2 * N> A;
+  gather_q<N>(Qi, M, modes, A);
+  double S[tri_size(2 * NB)];
+  if constexpr (NX == 0) {
+#pragma unroll
+    for (int q = 0; q < tri_size(2 * NB); ++q) S[q] = A.a[q];
+  } else {
+    Tri<2 * N - 2> A1;
+    const double det0 = fma(A.a[0], A.a[2], -A.a[1] * A.a[1]);
+    bad |= !(det0 > 0.0);
+    schur_leading_block<2 * N>(A, 1.0 / det0, A1);
+    if constexpr (NX == 1) {
+#pragma unroll
+      for (int q = 0; q < tri_size(2 * NB); ++q) S[q] = A1.a[q];
+    } else {
+      Tri<2 * N - 4> A2;
+      const double det1 = fma(A1.a[0], A1.a[2], -A1.a[1] * A1.a[1]);
+      bad |= !(det1 > 0.0);
+      schur_leading_block<2 * N - 2>(A1, 1.0 / det1, A2);
+      if constexpr (NX == 2) {
+#pragma unroll
+        for (int q = 0; q < tri_size(2 * NB); ++q) S[q] = A2.a[q];
+      } else {
+        Tri<2 * N - 6> A3;
+        const double det2 = fma(A2.a[0], A2.a[2], -A2.a[1] * A2.a[1]);
+        bad |= !(det2 > 0.0);
+        schur_leading_block<2 * N - 4>(A2, 1.0 / det2, A3);
+        if constexpr (NX == 3) {
+#pragma unroll
+          for (int q = 0; q < tri_size(2 * NB); ++q) S[q] = A3.a[q];
+        } else {
+          static_assert(NX <= 4, "at most four eliminated blocks");
+          Tri<2 * N - 8> A4;
+          const double det3 = fma(A3.a[0], A3.a[2], -A3.a[1] * A3.a[1]);
+          bad |= !(det3 > 0.0);
+          schur_leading_block<2 * N - 6>(A3, 1.0 / det3, A4);
+#pragma unroll
+          for (int q = 0; q < tri_size(2 * NB); ++q) S[q] = A4.a[q];
+        }
+      }
+    }
+  }
+  if constexpr (NB == 1) {
+    // inverse of the 2x2 Schur complement [[s00, s10], [s10, s11]]
+    const double det = fma(S[0], S[2], -S[1] * S[1]);
+    bad |= !(det > 0.0);
+    const double inv = 1.0 / det;
+    G[0] = S[2] * inv;
+    G[1] = -S[1] * inv;
+    G[2] = -S[1] * inv;
+    G[3] = S[0] * inv;
+  } else {
+    // [[A, Bm], [Bm^T, C]]^{-1} off-diagonal block = -A^{-1} Bm Sc^{-1},
+    // Sc = C - Bm^T A^{-1} Bm.  Packed 4x4: A = (0,0),(1,0),(1,1);
+    // Bm^T rows 2,3 cols 0,1; C = (2,2),(3,2),(3,3).
+    const double a00 = S[tri(0, 0)], a10 = S[tri(1, 0)], a11 = S[tri(1, 1)];
+    const double b00 = S[tri(2, 0)], b01 = S[tri(3, 0)], b10 = S[tri(2, 1)], b11 = S[tri(3, 1)];
+    // Bm = [[b00, b01], [b10, b11]] (rows: A's modes, cols: C's modes)
+    const double da = fma(a00, a11, -a10 * a10);
+    bad |= !(da > 0.0);
+    const double ia = 1.0 / da;
+    const double ai00 = a11 * ia, ai01 = -a10 * ia, ai11 = a00 * ia;
+    // Y = A^{-1} Bm
+    const double y00 = ai00 * b00 + ai01 * b10, y01 = ai00 * b01 + ai01 * b11;
+    const double y10 = ai01 * b00 + ai11 * b10, y11 = ai01 * b01 + ai11 * b11;
+    // Sc = C - Bm^T Y
+    const double c00 = S[tri(2, 2)] - (b00 * y00 + b10 * y10);
+    const double c01 = S[tri(3, 2)] - (b00 * y01 + b10 * y11);
+    const double c11 = S[tri(3, 3)] - (b01 * y01 + b11 * y11);
+    const double dc = fma(c00, c11, -c01 * c01);
+    bad |= !(dc > 0.0);
+    const double ic = 1.0 / dc;
+    const double si00 = c11 * ic, si01 = -c01 * ic, si11 = c00 * ic;
+    // -Y Sc^{-1}
+    G[0] = -(y00 * si00 + y01 * si01);
+    G[1] = -(y00 * si01 + y01 * si11);
+    G[2] = -(y10 * si00 + y11 * si01);
+    G[3] = -(y10 * si01 + y11 * si11);
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void base_inverse_dispatch(const double* __restrict__ Qi, int M,
+                                                      const int* modes, int nx, double (&G)[4],
+                                                      bool& bad) {
+  switch (nx) {
+    case 0: base_inverse<0, NB>(Qi, M, modes, G, bad); break;
+    case 1: base_inverse<1, NB>(Qi, M, modes, G, bad); break;
+    case 2: base_inverse<2, NB>(Qi, M, modes, G, bad); break;
+    case 3: base_inverse<3, NB>(Qi, M, modes, G, bad); break;
+    default: if constexpr (NB == 1) base_inverse<4, 1>(Qi, M, modes, G, bad); break;
+  }
+}
+
+// One wavefront per mode pair (i <= j): the 2x2 block of dL/dsigma.
+__global__ __launch_bounds__(kWave) void sigma_bar_kernel(const double* __restrict__ Qi, int M, int K,
+                                                          Offsets o,
+                                                          const uint64_t* __restrict__ bin,
+                                                          const double* __restrict__ ptab,
+                                                          const double* __restrict__ pbar,
+                                                          double* __restrict__ gsig,
+                                                          DeviceStatus* __restrict__ st) {
+  // pair index -> (i, j), i <= j, colex over pairs with repetition:
+  // blockIdx = j (j+1)/2 + i
+  const int64_t pid = blockIdx.x;
+  int j = (int)((sqrt(8.0 * (double)pid + 1.0) - 1.0) / 2.0);
+  while ((int64_t)j * (j + 1) / 2 > pid) --j;
+  while ((int64_t)(j + 1) * (j + 2) / 2 <= pid) ++j;
+  const int i = (int)(pid - (int64_t)j * (j + 1) / 2);
+  const int lane = threadIdx.x;
+  int base[2] = {i, j};
+  const int nb = (i == j) ? 1 : 2;
+  const int u = M - nb;
+  const uint64_t nx = count_sized(bin, 0, K - nb, u);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  bool bad = false;
+  for (uint64_t q = lane; q < nx; q += kWave) {
+    int jx;
+    uint64_t rx;
+    flat_to_sized(bin, q, 0, K - nb, u, &jx, &rx);
+    int xc[kMaxOrder], X[kMaxOrder], T[kMaxOrder];
+    unrank_dyn(bin, rx, jx, u, xc);
+    complement_modes(xc, jx, base, nb, X);
+    const int n = merge_sorted(base, nb, X, jx, T);
+    const int64_t at = o.off[n] + (int64_t)rank_sorted(bin, T, n);
+    const double w = -0.5 * pbar[at] * ptab[at];
+    int modes[kMaxOrder];
+    for (int t = 0; t < jx; ++t) modes[t] = X[t];
+    for (int t = 0; t < nb; ++t) modes[jx + t] = base[t];
+    double G[4];
+    if (nb == 1) base_inverse_dispatch<1>(Qi, M, modes, jx, G, bad);
+    else base_inverse_dispatch<2>(Qi, M, modes, jx, G, bad);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[e] = fma(w, G[e], acc[e]);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) acc[e] = wave_sum(acc[e]);
+  if (bad) latch_failure(st, 0, pid);
+  if (lane == 0) {
+    const size_t n2 = 2 * (size_t)M;
+    // interleaved (2i + a, 2j + b) -> xxpp (i + a M, j + b M)
+    const size_t xi = i, pi = i + M, xj = j, pj = j + M;
+    gsig[xi * n2 + xj] = acc[0];
+    gsig[xi * n2 + pj] = acc[1];
+    gsig[pi * n2 + xj] = acc[2];
+    gsig[pi * n2 + pj] = acc[3];
+    if (i != j) {
+      gsig[xj * n2 + xi] = acc[0];
+      gsig[pj * n2 + xi] = acc[1];
+      gsig[xj * n2 + pi] = acc[2];
+      gsig[pj * n2 + pi] = acc[3];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(int M, int K, int flags, const double* Qi, const uint64_t* binom,
+                          const double* m, const double* ptab, const double* gm, const double* gk,
+                          double* d1, double* mbar, double* pbar, double* gsig, DeviceStatus* st,
+                          hipStream_t s) {
+  Offsets o{};
+  o.off[1] = 0;
+  for (int d = 1; d <= kMaxOrder; ++d) o.off[d + 1] = o.off[d] + (d <= K ? (int64_t)host_binom(M, d) : 0);
+  hipError_t e = hipSuccess;
+  const int parity = (flags & GBS_PARITY) ? 1 : 0;
+  if (K >= 2 && gk) {
+    e = timing_begin(s, GBS_STAGE_ADJOINT, 0);
+    const int64_t n1 = o.off[K];
+    const int grid = (int)std::min<int64_t>((n1 + 255) / 256, 65535);
+    if (e == hipSuccess) hipLaunchKernelGGL(d1_kernel, dim3(grid), dim3(256), 0, s, m, M, K, o, binom, d1);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = timing_end(s);
+  }
+  for (int k = 1; k <= K && e == hipSuccess; ++k) {
+    e = timing_begin(s, GBS_STAGE_ADJOINT, k);
+    if (e == hipSuccess)
+      hipLaunchKernelGGL(mbar_kernel, dim3((unsigned)host_binom(M, k)), dim3(kWave), 0, s, M, K, k,
+                         o, binom, gm, gk, d1, mbar);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = timing_end(s);
+  }
+  for (int t = 1; t <= K && e == hipSuccess; ++t) {
+    e = timing_begin(s, GBS_STAGE_ADJOINT, t);
+    if (e == hipSuccess)
+      hipLaunchKernelGGL(pbar_kernel, dim3((unsigned)host_binom(M, t)), dim3(kWave), 0, s, M, K, t,
+                         parity, o, binom, mbar, pbar);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = timing_end(s);
+  }
+  if (e == hipSuccess) {
+    e = timing_begin(s, GBS_STAGE_ADJOINT, 0);
+    const unsigned pairs = (unsigned)((int64_t)M * (M + 1) / 2);
+    if (e == hipSuccess)
+      hipLaunchKernelGGL(sigma_bar_kernel, dim3(pairs), dim3(kWave), 0, s, Qi, M, K, o, binom, ptab,
+                         pbar, gsig, st);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = timing_end(s);
+  }
+  return e;
+}
+
+}  // namespace gbs

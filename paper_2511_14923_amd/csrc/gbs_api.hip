@@ -152,27 +152,27 @@ ForwardScratch layout_scratch(char* base, int M, bool mixed) {
   return s;
 }
 
-// Copy the device status back and report it (synchronising unless ASYNC).
-gbs_status finish_call(DeviceStatus* dev_status, void* scratch, int32_t flags, hipStream_t s) {
+// Queue the copy of the device status word to this thread's pinned slot.
+static gbs_status status_enqueue(DeviceStatus* dev_status, hipStream_t s) {
   if (!t_err.host_status) {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&t_err.host_status), sizeof(DeviceStatus),
                                  hipHostMallocDefault);
     if (e != hipSuccess) {
       t_err.host_status = nullptr;
-      (void)hipFreeAsync(scratch, s);
       return to_status(e);
     }
   }
-  hipError_t e = hipMemcpyAsync(t_err.host_status, dev_status, sizeof(DeviceStatus),
-                                hipMemcpyDeviceToHost, s);
-  hipError_t e2 = hipFreeAsync(scratch, s);
-  if (e == hipSuccess) e = e2;
-  if (e != hipSuccess) return to_status(e);
+  return to_status(hipMemcpyAsync(t_err.host_status, dev_status, sizeof(DeviceStatus),
+                                  hipMemcpyDeviceToHost, s));
+}
+
+// Wait for the stream (unless ASYNC) and report the copied status.
+static gbs_status status_wait(int32_t flags, hipStream_t s) {
   if (flags & GBS_ASYNC) {
     t_err.pending_async = true;
     return GBS_OK;
   }
-  e = hipStreamSynchronize(s);
+  hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return to_status(e);
   t_err.pending_async = false;
   if (t_err.host_status->flag) {
@@ -183,6 +183,24 @@ gbs_status finish_call(DeviceStatus* dev_status, void* scratch, int32_t flags, h
   t_err.order = 0;
   t_err.rank = -1;
   return GBS_OK;
+}
+
+gbs_status finish_status(DeviceStatus* dev_status, int32_t flags, hipStream_t s) {
+  t_err.order = 0;
+  t_err.rank = -1;
+  gbs_status st = status_enqueue(dev_status, s);
+  if (st != GBS_OK) return st;
+  return status_wait(flags, s);
+}
+
+// Report the status, then release the call's stream-ordered scratch (the free
+// is queued after the status copy on the same stream).
+gbs_status finish_call(DeviceStatus* dev_status, void* scratch, int32_t flags, hipStream_t s) {
+  gbs_status st = status_enqueue(dev_status, s);
+  hipError_t e = hipFreeAsync(scratch, s);
+  if (st != GBS_OK) return st;
+  if (e != hipSuccess) return to_status(e);
+  return status_wait(flags, s);
 }
 
 gbs_status run_forward(int32_t M, const double* sigma, int32_t K, int32_t flags, double* corr,
@@ -214,7 +232,7 @@ gbs_status run_forward(int32_t M, const double* sigma, int32_t K, int32_t flags,
     e = timing_begin(s, GBS_STAGE_FORWARD, d);
     if (e == hipSuccess)
       e = launch_forward(d, M, flags, sc.Qi, sc.pk, sc.E, ctx->binom, corr ? corr + off : nullptr,
-                         cum ? cum + off : nullptr, sc.st, s);
+                         cum ? cum + off : nullptr, nullptr, sc.st, s);
     if (e == hipSuccess) e = timing_end(s);
   }
   if (e != hipSuccess) {
@@ -222,6 +240,57 @@ gbs_status run_forward(int32_t M, const double* sigma, int32_t K, int32_t flags,
     return to_status(e);
   }
   return finish_call(sc.st, scratch, flags, s);
+}
+
+gbs_status run_adjoint(int32_t M, const double* sigma, int32_t K, int32_t flags,
+                       const double* gm, const double* gk, double* gsig, void* stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e;
+  DeviceContext* ctx = current_context(&e);
+  if (!ctx) return to_status(e);
+  const size_t N = (size_t)gbs_total_outputs(M, K);
+  const size_t nq = 4 * (size_t)M * M;
+  size_t off = 0;
+  const size_t oQ = off; off += align256(nq * sizeof(double));
+  const size_t oP = off; off += align256(N * sizeof(double));
+  const size_t oM = off; off += align256(N * sizeof(double));
+  const size_t oD = off; off += align256(N * sizeof(double));
+  const size_t oMb = off; off += align256(N * sizeof(double));
+  const size_t oPb = off; off += align256(N * sizeof(double));
+  const size_t oSt = off; off += align256(sizeof(DeviceStatus));
+  void* scratch = nullptr;
+  e = hipMallocAsync(&scratch, off, s);
+  if (e != hipSuccess) return to_status(e);
+  char* b = static_cast<char*>(scratch);
+  double* Qi = reinterpret_cast<double*>(b + oQ);
+  double* ptab = reinterpret_cast<double*>(b + oP);
+  double* m = reinterpret_cast<double*>(b + oM);
+  double* d1 = reinterpret_cast<double*>(b + oD);
+  double* mbar = reinterpret_cast<double*>(b + oMb);
+  double* pbar = reinterpret_cast<double*>(b + oPb);
+  DeviceStatus* st = reinterpret_cast<DeviceStatus*>(b + oSt);
+  t_err.order = 0;
+  t_err.rank = -1;
+  timing_start_call((flags & GBS_TIMING) != 0);
+  e = launch_clear_status(st, s);
+  if (e == hipSuccess) e = timing_begin(s, GBS_STAGE_BUILD_Q, 0);
+  if (e == hipSuccess) e = launch_build_q(sigma, M, Qi, s);
+  if (e == hipSuccess) e = timing_end(s);
+  for (int d = 1; d <= K && e == hipSuccess; ++d) {
+    const int64_t o = gbs_order_offset(M, d);
+    e = timing_begin(s, GBS_STAGE_FORWARD, d);
+    if (e == hipSuccess)
+      e = launch_forward(d, M, flags & GBS_PARITY, Qi, nullptr, nullptr, ctx->binom, m + o, nullptr,
+                         ptab + o, st, s);
+    if (e == hipSuccess) e = timing_end(s);
+  }
+  if (e == hipSuccess)
+    e = launch_adjoint(M, K, flags, Qi, ctx->binom, m, ptab, gm, gk, d1, mbar, pbar, gsig, st, s);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(scratch, s);
+    return to_status(e);
+  }
+  return finish_call(st, scratch, flags, s);
 }
 
 }  // namespace gbs
@@ -296,6 +365,14 @@ gbs_status gbs_cumulants(int32_t M, const double* sigma, int32_t max_order, int3
   return run_forward(M, sigma, max_order, flags, corr, cum, stream);
 }
 
+gbs_status gbs_cumulant_grad(int32_t M, const double* sigma, int32_t max_order, int32_t flags,
+                             const double* grad_corr, const double* grad_cum, double* grad_sigma,
+                             void* stream) {
+  if (!valid_problem(M, max_order, flags) || !sigma || !grad_sigma) return GBS_E_INVALID_ARG;
+  if (flags & GBS_MIXED) return GBS_E_UNSUPPORTED;
+  return run_adjoint(M, sigma, max_order, flags, grad_corr, grad_cum, grad_sigma, stream);
+}
+
 gbs_status gbs_last_error(int32_t* order, int64_t* rank) {
   if (t_err.pending_async && t_err.host_status) {
     // valid once the stream of the last asynchronous call has completed
@@ -342,21 +419,3 @@ const char* gbs_status_string(gbs_status s) {
 
 }  // extern "C"
 
-// ---- entry points implemented in later sources (temporary) ----
-extern "C" {
-gbs_status gbs_cumulant_grad(int32_t M, const double* sigma, int32_t K, int32_t flags,
-                             const double*, const double*, double* grad_sigma, void*) {
-  if (!valid_problem(M, K, flags) || !sigma || !grad_sigma) return GBS_E_INVALID_ARG;
-  return GBS_E_UNSUPPORTED;
-}
-gbs_status gbs_cumulants_batched(int32_t n, const gbs_instance* inst, int32_t, int32_t, void*) {
-  if (n < 1 || !inst) return GBS_E_INVALID_ARG;
-  return GBS_E_UNSUPPORTED;
-}
-gbs_status gbs_autotune_batched(int32_t n, const gbs_instance* inst, int32_t, int32_t, void*,
-                                gbs_tuning*) {
-  if (n < 1 || !inst) return GBS_E_INVALID_ARG;
-  return GBS_E_UNSUPPORTED;
-}
-gbs_status gbs_set_tuning(int32_t, int32_t, const gbs_tuning*) { return GBS_E_UNSUPPORTED; }
-}

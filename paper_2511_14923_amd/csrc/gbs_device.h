@@ -47,6 +47,57 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
   return y;
 }
 
+// Packed lower triangle of an N x N symmetric matrix.
+template <int N>
+struct Tri {
+  double a[tri_size(N)];
+};
+
+// Schur complement of the leading 2x2 block P of A (n x n, n >= 4):
+//   S = A_rr - A_r0 P^{-1} A_0r,  P^{-1} = adj(P) / det(P).
+// Returns det(P); inv_det = 1/det(P) is supplied by the caller (it usually
+// has det(P)^(-1/2) already).
+template <int n>
+__device__ __forceinline__ void schur_leading_block(const Tri<n>& A, double inv_det, Tri<n - 2>& S) {
+  const double a00 = A.a[0], a10 = A.a[1], a11 = A.a[2];
+  double u0[n], u1[n];
+#pragma unroll
+  for (int i = 2; i < n; ++i) {
+    const double c0 = A.a[tri(i, 0)], c1 = A.a[tri(i, 1)];
+    u0[i] = fma(a11, c0, -a10 * c1) * inv_det;
+    u1[i] = fma(a00, c1, -a10 * c0) * inv_det;
+  }
+#pragma unroll
+  for (int i = 2; i < n; ++i) {
+#pragma unroll
+    for (int j = 2; j <= i; ++j) {
+      S.a[tri(i - 2, j - 2)] =
+          fma(-A.a[tri(i, 1)], u1[j], fma(-A.a[tri(i, 0)], u0[j], A.a[tri(i, j)]));
+    }
+  }
+}
+
+// Gather the 2n x 2n principal block of the interleaved Q for modes s[0..n-1]
+// (in the given order: block i of the result is mode s[i]).
+template <int n>
+__device__ __forceinline__ void gather_q(const double* __restrict__ Qi, int M, const int* s,
+                                         Tri<2 * n>& A) {
+  const size_t ldq = 2 * (size_t)M;
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      const double* q = Qi + (size_t)(2 * s[i]) * ldq + 2 * s[j];
+      const double2 q0 = *reinterpret_cast<const double2*>(q);
+      const double2 q1 = *reinterpret_cast<const double2*>(q + ldq);
+      A.a[tri(2 * i, 2 * j)] = q0.x;
+      A.a[tri(2 * i + 1, 2 * j)] = q1.x;
+      A.a[tri(2 * i + 1, 2 * j + 1)] = q1.y;
+      if (i != j) A.a[tri(2 * i, 2 * j + 1)] = q0.y;
+    }
+  }
+}
+
 // Colex unranking.  bin[k * ld + n] = C(n, k) for k = 1..D, n = 0..M.
 // Writes s[0] < s[1] < ... < s[D-1] with sum_j C(s[j], j+1) = r.
 template <int D, typename Table>

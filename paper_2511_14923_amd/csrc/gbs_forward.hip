@@ -24,102 +24,9 @@
 #include <hip/hip_runtime.h>
 
 #include "gbs_internal.h"
+#include "gbs_subset.h"
 
 namespace gbs {
-
-template <int N>
-struct Tri {
-  double a[tri_size(N)];
-};
-
-// p[MASK | ...] for every subset of the remaining blocks K..D-1, given the
-// matrix A over those blocks (Schur complement with respect to the blocks in
-// MASK, restriction with respect to the others) and pT = p(MASK).
-template <int D, int K, unsigned MASK>
-__device__ __forceinline__ void principal_minors(const Tri<2 * (D - K)>& A, double pT,
-                                                 double (&p)[1 << D], bool& bad) {
-  constexpr int n = 2 * (D - K);
-  const double a00 = A.a[0], a10 = A.a[1], a11 = A.a[2];
-  const double det = fma(a00, a11, -a10 * a10);
-  bad |= !(a00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
-  const double y = rsqrt_f64(det);  // det(Q_b | eliminated)^(-1/2)
-  if constexpr (n == 2) {
-    p[MASK | (1u << K)] = pT * y;
-    p[MASK] = pT;
-  } else {
-    const double inv = y * y;
-    double u0[n], u1[n];
-#pragma unroll
-    for (int i = 2; i < n; ++i) {
-      const double c0 = A.a[tri(i, 0)], c1 = A.a[tri(i, 1)];
-      u0[i] = fma(a11, c0, -a10 * c1) * inv;
-      u1[i] = fma(a00, c1, -a10 * c0) * inv;
-    }
-    Tri<n - 2> S;
-#pragma unroll
-    for (int i = 2; i < n; ++i) {
-#pragma unroll
-      for (int j = 2; j <= i; ++j) {
-        S.a[tri(i - 2, j - 2)] =
-            fma(-A.a[tri(i, 1)], u1[j], fma(-A.a[tri(i, 0)], u0[j], A.a[tri(i, j)]));
-      }
-    }
-    principal_minors<D, K + 1, MASK | (1u << K)>(S, pT * y, p, bad);
-    Tri<n - 2> R;
-#pragma unroll
-    for (int i = 2; i < n; ++i) {
-#pragma unroll
-      for (int j = 2; j <= i; ++j) R.a[tri(i - 2, j - 2)] = A.a[tri(i, j)];
-    }
-    principal_minors<D, K + 1, MASK>(R, pT, p, bad);
-  }
-}
-
-// m[B] for every B subset S from the vacuum probabilities (subset zeta transform).
-template <int D, int CONV>
-__device__ __forceinline__ void correlators_from_vacuum(const double (&p)[1 << D],
-                                                        double (&m)[1 << D]) {
-  constexpr int NS = 1 << D;
-#pragma unroll
-  for (int T = 0; T < NS; ++T) {
-    const int t = popcount_c((unsigned)T);
-    if (CONV == GBS_CLICK) {
-      m[T] = (t & 1) ? -p[T] : p[T];
-    } else {
-      m[T] = ((t & 1) ? -1.0 : 1.0) * (double)(1 << t) * p[T];
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < D; ++b) {
-#pragma unroll
-    for (int T = 0; T < NS; ++T) {
-      if (T & (1 << b)) m[T] += m[T ^ (1 << b)];
-    }
-  }
-  if (CONV == GBS_PARITY) {
-#pragma unroll
-    for (int T = 0; T < NS; ++T)
-      if (popcount_c((unsigned)T) & 1) m[T] = -m[T];
-  }
-}
-
-// Cumulant of the full set from all sub-correlators (m[0] = 1).
-template <int D>
-__device__ __forceinline__ double cumulant_from_correlators(const double (&m)[1 << D]) {
-  constexpr unsigned top = 1u << (D - 1);
-  constexpr int NR = 1 << (D - 1);
-  double k[NR];
-#pragma unroll
-  for (int B = 0; B < NR; ++B) {
-    double v = m[B | top];
-#pragma unroll
-    for (int R = 0; R < NR; ++R) {
-      if (R != B && (R & B) == R) v = fma(-k[R], m[B ^ R], v);
-    }
-    k[B] = v;
-  }
-  return k[NR - 1];
-}
 
 template <int D, int CONV, bool WRITE_CORR, bool WRITE_CUM, bool LDS_BIN>
 __global__ __launch_bounds__(256) void forward_fp64_kernel(const double* __restrict__ Qi, int M,
@@ -127,6 +34,7 @@ __global__ __launch_bounds__(256) void forward_fp64_kernel(const double* __restr
                                                            const uint64_t* __restrict__ binom,
                                                            double* __restrict__ corr,
                                                            double* __restrict__ cum,
+                                                           double* __restrict__ ptab,
                                                            DeviceStatus* __restrict__ st) {
   extern __shared__ uint64_t sbin[];
   const uint64_t* bin;
@@ -148,32 +56,13 @@ __global__ __launch_bounds__(256) void forward_fp64_kernel(const double* __restr
 
   int s[D];
   colex_unrank<D>(r, M, bin, ld, s);
-
-  Tri<2 * D> A;
-  const size_t ldq = 2 * (size_t)M;
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      const double* q = Qi + (size_t)(2 * s[i]) * ldq + 2 * s[j];
-      const double2 q0 = *reinterpret_cast<const double2*>(q);
-      const double2 q1 = *reinterpret_cast<const double2*>(q + ldq);
-      A.a[tri(2 * i, 2 * j)] = q0.x;
-      A.a[tri(2 * i + 1, 2 * j)] = q1.x;
-      A.a[tri(2 * i + 1, 2 * j + 1)] = q1.y;
-      if (i != j) A.a[tri(2 * i, 2 * j + 1)] = q0.y;
-    }
-  }
-
-  double p[1 << D];
+  double mS, kS, pS;
   bool bad = false;
-  principal_minors<D, 0, 0u>(A, 1.0, p, bad);
+  subset_fp64<D, CONV, WRITE_CUM>(Qi, M, s, mS, kS, pS, bad);
   if (bad) latch_failure(st, D, (int64_t)r);
-
-  double m[1 << D];
-  correlators_from_vacuum<D, CONV>(p, m);
-  if constexpr (WRITE_CORR) corr[r] = m[(1 << D) - 1];
-  if constexpr (WRITE_CUM) cum[r] = cumulant_from_correlators<D>(m);
+  if (ptab) ptab[r] = pS;
+  if constexpr (WRITE_CORR) corr[r] = mS;
+  if constexpr (WRITE_CUM) cum[r] = kS;
   }
 }
 
@@ -214,7 +103,7 @@ hipError_t launch_clear_status(DeviceStatus* st, hipStream_t s) {
 
 template <int D, int CONV, bool WC, bool WK>
 static hipError_t launch_fp64_t(int M, const double* Qi, const uint64_t* binom, double* corr,
-                                double* cum, DeviceStatus* st, hipStream_t s) {
+                                double* cum, double* ptab, DeviceStatus* st, hipStream_t s) {
   const uint64_t count = host_binom(M, D);
   if (count == 0) return hipSuccess;
   const int block = 256;
@@ -222,27 +111,28 @@ static hipError_t launch_fp64_t(int M, const double* Qi, const uint64_t* binom, 
   const size_t lds = (size_t)(D + 1) * (M + 1) * sizeof(uint64_t);
   if (lds <= 48 * 1024) {
     hipLaunchKernelGGL((forward_fp64_kernel<D, CONV, WC, WK, true>), dim3((unsigned)grid),
-                       dim3(block), lds, s, Qi, M, count, binom, corr, cum, st);
+                       dim3(block), lds, s, Qi, M, count, binom, corr, cum, ptab, st);
   } else {
     hipLaunchKernelGGL((forward_fp64_kernel<D, CONV, WC, WK, false>), dim3((unsigned)grid),
-                       dim3(block), 0, s, Qi, M, count, binom, corr, cum, st);
+                       dim3(block), 0, s, Qi, M, count, binom, corr, cum, ptab, st);
   }
   return hipGetLastError();
 }
 
 template <int D, int CONV>
 static hipError_t launch_fp64_w(int M, const double* Qi, const uint64_t* binom, double* corr,
-                                double* cum, DeviceStatus* st, hipStream_t s) {
-  if (corr && cum) return launch_fp64_t<D, CONV, true, true>(M, Qi, binom, corr, cum, st, s);
-  if (corr) return launch_fp64_t<D, CONV, true, false>(M, Qi, binom, corr, cum, st, s);
-  return launch_fp64_t<D, CONV, false, true>(M, Qi, binom, corr, cum, st, s);
+                                double* cum, double* ptab, DeviceStatus* st, hipStream_t s) {
+  if (corr && cum) return launch_fp64_t<D, CONV, true, true>(M, Qi, binom, corr, cum, ptab, st, s);
+  if (corr) return launch_fp64_t<D, CONV, true, false>(M, Qi, binom, corr, cum, ptab, st, s);
+  return launch_fp64_t<D, CONV, false, true>(M, Qi, binom, corr, cum, ptab, st, s);
 }
 
 template <int D>
 static hipError_t launch_fp64_c(int M, int flags, const double* Qi, const uint64_t* binom,
-                                double* corr, double* cum, DeviceStatus* st, hipStream_t s) {
-  if (flags & GBS_PARITY) return launch_fp64_w<D, GBS_PARITY>(M, Qi, binom, corr, cum, st, s);
-  return launch_fp64_w<D, GBS_CLICK>(M, Qi, binom, corr, cum, st, s);
+                                double* corr, double* cum, double* ptab, DeviceStatus* st,
+                                hipStream_t s) {
+  if (flags & GBS_PARITY) return launch_fp64_w<D, GBS_PARITY>(M, Qi, binom, corr, cum, ptab, st, s);
+  return launch_fp64_w<D, GBS_CLICK>(M, Qi, binom, corr, cum, ptab, st, s);
 }
 
 hipError_t launch_forward_mixed(int d, int M, int flags, const double* pk, const float* E,
@@ -251,15 +141,15 @@ hipError_t launch_forward_mixed(int d, int M, int flags, const double* pk, const
 
 hipError_t launch_forward(int d, int M, int flags, const double* Qi, const double* pk,
                           const float* E, const uint64_t* binom, double* corr, double* cum,
-                          DeviceStatus* st, hipStream_t s) {
+                          double* ptab, DeviceStatus* st, hipStream_t s) {
   if (!corr && !cum) return hipSuccess;
   if (flags & GBS_MIXED) return launch_forward_mixed(d, M, flags, pk, E, binom, corr, cum, st, s);
   switch (d) {
-    case 1: return launch_fp64_c<1>(M, flags, Qi, binom, corr, cum, st, s);
-    case 2: return launch_fp64_c<2>(M, flags, Qi, binom, corr, cum, st, s);
-    case 3: return launch_fp64_c<3>(M, flags, Qi, binom, corr, cum, st, s);
-    case 4: return launch_fp64_c<4>(M, flags, Qi, binom, corr, cum, st, s);
-    case 5: return launch_fp64_c<5>(M, flags, Qi, binom, corr, cum, st, s);
+    case 1: return launch_fp64_c<1>(M, flags, Qi, binom, corr, cum, ptab, st, s);
+    case 2: return launch_fp64_c<2>(M, flags, Qi, binom, corr, cum, ptab, st, s);
+    case 3: return launch_fp64_c<3>(M, flags, Qi, binom, corr, cum, ptab, st, s);
+    case 4: return launch_fp64_c<4>(M, flags, Qi, binom, corr, cum, ptab, st, s);
+    case 5: return launch_fp64_c<5>(M, flags, Qi, binom, corr, cum, ptab, st, s);
     default: return hipErrorInvalidValue;
   }
 }

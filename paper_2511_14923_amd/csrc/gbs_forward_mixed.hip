@@ -24,66 +24,9 @@
 #include <hip/hip_runtime.h>
 
 #include "gbs_internal.h"
+#include "gbs_subset.h"
 
 namespace gbs {
-
-template <int N>
-struct TriF {
-  float a[tri_size(N)];
-};
-
-struct Neumaier {
-  double s = 0.0, c = 0.0;
-  __device__ __forceinline__ void add(double x) {
-    const double t = s + x;
-    c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
-    s = t;
-  }
-  __device__ __forceinline__ double value() const { return s + c; }
-};
-
-template <int D, int K, unsigned MASK>
-__device__ __forceinline__ void minors_mixed(const TriF<2 * (D - K)>& F, float rho,
-                                             float (&rhoT)[1 << D], bool& bad) {
-  constexpr int n = 2 * (D - K);
-  const float f00 = F.a[0], f10 = F.a[1], f11 = F.a[2];
-  const float delta = f00 + f11 + fmaf(f00, f11, -f10 * f10);
-  const float onep = 1.0f + delta;
-  bad |= !(onep > 0.0f) || !(1.0f + f00 > 0.0f) || !(onep < INFINITY);
-  const float y = __builtin_amdgcn_rsqf(onep);
-  const float inv = y * y;
-  const float eta = -delta * inv * __builtin_amdgcn_rcpf(1.0f + y);
-  const float rho_c = rho + fmaf(rho, eta, eta);
-  if constexpr (n == 2) {
-    rhoT[MASK | (1u << K)] = rho_c;
-    rhoT[MASK] = rho;
-  } else {
-    const float g00 = 1.0f + f00, g11 = 1.0f + f11;
-    float u0[n], u1[n];
-#pragma unroll
-    for (int i = 2; i < n; ++i) {
-      const float c0 = F.a[tri(i, 0)], c1 = F.a[tri(i, 1)];
-      u0[i] = fmaf(g11, c0, -f10 * c1) * inv;
-      u1[i] = fmaf(g00, c1, -f10 * c0) * inv;
-    }
-    TriF<n - 2> S;
-#pragma unroll
-    for (int i = 2; i < n; ++i) {
-#pragma unroll
-      for (int j = 2; j <= i; ++j)
-        S.a[tri(i - 2, j - 2)] =
-            fmaf(-F.a[tri(i, 1)], u1[j], fmaf(-F.a[tri(i, 0)], u0[j], F.a[tri(i, j)]));
-    }
-    minors_mixed<D, K + 1, MASK | (1u << K)>(S, rho_c, rhoT, bad);
-    TriF<n - 2> R;
-#pragma unroll
-    for (int i = 2; i < n; ++i) {
-#pragma unroll
-      for (int j = 2; j <= i; ++j) R.a[tri(i - 2, j - 2)] = F.a[tri(i, j)];
-    }
-    minors_mixed<D, K + 1, MASK>(R, rho, rhoT, bad);
-  }
-}
 
 template <int D, int CONV, bool WRITE_CORR, bool WRITE_CUM, bool LDS_BIN>
 __global__ __launch_bounds__(256) void forward_mixed_kernel(const double* __restrict__ pk,
@@ -114,111 +57,12 @@ __global__ __launch_bounds__(256) void forward_mixed_kernel(const double* __rest
   int s[D];
   colex_unrank<D>(r, M, bin, ld, s);
 
-  constexpr int NS = 1 << D;
-  double p1[D];
-#pragma unroll
-  for (int i = 0; i < D; ++i) p1[i] = pk[s[i]];
-
-  float rhoT[NS];
+  double mS, kS;
   bool bad = false;
-  if constexpr (D == 1) {
-    rhoT[0] = 0.0f;
-    rhoT[1] = 0.0f;
-  } else {
-    TriF<2 * D> F;
-    const size_t lde = 2 * (size_t)M;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      F.a[tri(2 * i, 2 * i)] = 0.0f;
-      F.a[tri(2 * i + 1, 2 * i)] = 0.0f;
-      F.a[tri(2 * i + 1, 2 * i + 1)] = 0.0f;
-#pragma unroll
-      for (int j = 0; j < i; ++j) {
-        const float* q = E + (size_t)(2 * s[i]) * lde + 2 * s[j];
-        const float2 q0 = *reinterpret_cast<const float2*>(q);
-        const float2 q1 = *reinterpret_cast<const float2*>(q + lde);
-        F.a[tri(2 * i, 2 * j)] = q0.x;
-        F.a[tri(2 * i, 2 * j + 1)] = q0.y;
-        F.a[tri(2 * i + 1, 2 * j)] = q1.x;
-        F.a[tri(2 * i + 1, 2 * j + 1)] = q1.y;
-      }
-    }
-    minors_mixed<D, 0, 0u>(F, 0.0f, rhoT, bad);
-  }
+  subset_mixed<D, CONV, WRITE_CUM>(pk, E, M, s, mS, kS, bad);
   if (bad) latch_failure(st, D, (int64_t)r);
-
-  // FP64 assembly.  P_T by subset products; corrections c_T = P_T rho_T.
-  double P[NS];
-  P[0] = 1.0;
-#pragma unroll
-  for (int T = 1; T < NS; ++T) {
-    const int low = __builtin_ctz((unsigned)T);
-    P[T] = P[T & (T - 1)] * p1[low];
-  }
-  double g[NS];
-#pragma unroll
-  for (int T = 0; T < NS; ++T) {
-    const int t = popcount_c((unsigned)T);
-    const double c = P[T] * (double)rhoT[T];
-    g[T] = (CONV == GBS_CLICK) ? ((t & 1) ? -c : c) : ((t & 1) ? -1.0 : 1.0) * (double)(1 << t) * c;
-  }
-  // zeta transform of the corrections for every proper subset; the full set's
-  // correlator is accumulated term by term with compensation
-  Neumaier top;
-#pragma unroll
-  for (int T = 0; T < NS; ++T) top.add(g[T]);
-#pragma unroll
-  for (int b = 0; b < D; ++b) {
-#pragma unroll
-    for (int T = 0; T < NS; ++T)
-      if (T & (1 << b)) g[T] += g[T ^ (1 << b)];
-  }
-  // product parts
-  double base[NS];
-  base[0] = 1.0;
-#pragma unroll
-  for (int T = 1; T < NS; ++T) {
-    const int low = __builtin_ctz((unsigned)T);
-    const double f = (CONV == GBS_CLICK) ? (1.0 - p1[low]) : (2.0 * p1[low] - 1.0);
-    base[T] = base[T & (T - 1)] * f;
-  }
-  double m[NS];
-#pragma unroll
-  for (int T = 0; T < NS; ++T) {
-    const double corrT = (CONV == GBS_CLICK || !(popcount_c((unsigned)T) & 1)) ? g[T] : -g[T];
-    m[T] = base[T] + corrT;
-  }
-  {
-    const double corrS = (CONV == GBS_CLICK || !(D & 1)) ? top.value() : -top.value();
-    Neumaier full;
-    full.add(base[NS - 1]);
-    full.add(corrS);
-    m[NS - 1] = full.value();
-  }
-  if constexpr (WRITE_CORR) corr[r] = m[NS - 1];
-  if constexpr (WRITE_CUM) {
-    constexpr unsigned topbit = 1u << (D - 1);
-    constexpr int NR = 1 << (D - 1);
-    double k[NR];
-#pragma unroll
-    for (int B = 0; B < NR; ++B) {
-      if (B == NR - 1) {
-        Neumaier acc;
-        acc.add(m[B | topbit]);
-#pragma unroll
-        for (int R = 0; R < NR; ++R)
-          if (R != B && (R & B) == R) acc.add(-k[R] * m[B ^ R]);
-        k[B] = acc.value();
-      } else {
-        double v = m[B | topbit];
-#pragma unroll
-        for (int R = 0; R < NR; ++R)
-          if (R != B && (R & B) == R) v = fma(-k[R], m[B ^ R], v);
-        k[B] = v;
-      }
-    }
-    cum[r] = k[NR - 1];
-  }
+  if constexpr (WRITE_CORR) corr[r] = mS;
+  if constexpr (WRITE_CUM) cum[r] = kS;
   }
 }
 

@@ -39,13 +39,27 @@ void timing_start_call(bool enabled);
 hipError_t timing_begin(hipStream_t s, int stage, int order);
 hipError_t timing_end(hipStream_t s);
 
+// Status of a call: HIP error mapping, and the end of a call (copy the device
+// status word back; synchronise and report unless GBS_ASYNC).
+gbs_status to_status(hipError_t e);
+gbs_status finish_status(DeviceStatus* dev_status, int32_t flags, hipStream_t s);
+
 // Reset a status word (fill kernel, safe inside graph capture).
 hipError_t launch_clear_status(DeviceStatus* st, hipStream_t s);
 
 // Order-d forward pass over all C(M, d) subsets.
-// FP64 reads Qi; MIXED reads pk and E.  corr and/or cum may be null (not written).
+// FP64 reads Qi; MIXED reads pk and E.  corr and/or cum may be null (not
+// written); ptab (FP64 only, may be null) receives p(S) of every subset.
 hipError_t launch_forward(int d, int M, int flags, const double* Qi, const double* pk,
                           const float* E, const uint64_t* binom, double* corr, double* cum,
-                          DeviceStatus* st, hipStream_t s);
+                          double* ptab, DeviceStatus* st, hipStream_t s);
+
+// Vector-Jacobian product given the forward correlators m and vacuum
+// probabilities ptab of every subset (orders 1..K); d1, mbar, pbar are scratch
+// of N(M, K) doubles; gsig (2M x 2M, xxpp) is overwritten.
+hipError_t launch_adjoint(int M, int K, int flags, const double* Qi, const uint64_t* binom,
+                          const double* m, const double* ptab, const double* gm, const double* gk,
+                          double* d1, double* mbar, double* pbar, double* gsig, DeviceStatus* st,
+                          hipStream_t s);
 
 }  // namespace gbs

@@ -1,0 +1,153 @@
+"""GPU tests of the batched persistent launch (gbs_cumulants_batched), its HIP
+graph replay and the autotuner."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import gbs_inputs as G
+import oracle as O
+from parity import assert_within, fp64_tolerance
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_2511_14923_amd as P
+    assert torch.cuda.is_available()
+    P.lib()
+    return P
+
+
+def _alloc(batch, K, want_corr=True):
+    import torch
+    out = []
+    for inst in batch:
+        s = torch.from_numpy(inst.sigma).to("cuda:0")
+        n = O.total_outputs(inst.M, K)
+        corr = torch.empty(n, dtype=torch.float64, device="cuda:0") if want_corr else None
+        cum = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        out.append((inst.M, s, corr, cum))
+    return out
+
+
+def _singles(P, bufs, K, flags):
+    return [P.gbs_cumulants(M, s, K, flags) for (M, s, _, _) in bufs]
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2], ids=["fp64", "parity", "mixed"])
+def test_batch48_equals_single_calls(P, flags):
+    """The 48-instance M ~ U{40..144}, K = 4 workload: every instance's output
+    equals a separate gbs_cumulants call bit for bit."""
+    import torch
+    _say("case: batch48", flags)
+    batch = G.make_batch()
+    bufs = _alloc(batch, 4)
+    P.gbs_cumulants_batched(bufs, 4, flags)
+    torch.cuda.synchronize()
+    singles = _singles(P, bufs, 4, flags)
+    for (M, _, corr, cum), (c1, k1) in zip(bufs, singles):
+        assert torch.equal(corr, c1), M
+        assert torch.equal(cum, k1), M
+
+
+def test_batch48_against_oracle(P, c_oracle):
+    """Sampled outputs of every instance against the C oracle (FP64 tolerance)."""
+    import torch
+    _say("case: batch48 vs oracle")
+    batch = G.make_batch()
+    bufs = _alloc(batch, 4)
+    P.gbs_cumulants_batched(bufs, 4, 0)
+    torch.cuda.synchronize()
+    for i, (inst, (M, _, corr, cum)) in enumerate(zip(batch, bufs)):
+        corr, cum = corr.cpu().numpy(), cum.cpu().numpy()
+        for d in range(1, 5):
+            n = math.comb(M, d)
+            ranks = G.random_ranks(n, 400, seed=1000 * i + d)
+            rc, rk = O.c_forward_sample(inst.sigma, d, ranks)
+            vmu, vkap = O.c_error_floor(inst.sigma, d, ranks)
+            off = O.order_offset(M, d)
+            assert_within(corr[off + ranks], rc, fp64_tolerance(rc, vmu), f"inst {i} corr d={d}")
+            assert_within(cum[off + ranks], rk, fp64_tolerance(rk, vkap), f"inst {i} cum d={d}")
+
+
+def test_graph_replay_sees_new_inputs(P):
+    """Second and third calls replay the captured graph; the covariances are
+    rewritten in place between replays (with eager work in between) and every
+    replay matches fresh single-instance calls."""
+    import torch
+    _say("case: graph replay")
+    batch = G.make_batch(count=6, seed=77, m_range=(8, 30))
+    bufs = _alloc(batch, 3)
+    for rep in range(3):
+        if rep:
+            for (M, s, _, _) in bufs:  # new values, same buffers
+                s.add_(torch.eye(2 * M, dtype=torch.float64, device="cuda:0") * 0.01 * rep)
+        _ = torch.randn(1000, device="cuda:0").sum().item()  # eager work between replays
+        P.gbs_cumulants_batched(bufs, 3, 0)
+        torch.cuda.synchronize()
+        for (M, s, corr, cum) in bufs:
+            c1, k1 = P.gbs_cumulants(M, s, 3, 0)
+            assert torch.equal(corr, c1) and torch.equal(cum, k1), (rep, M)
+
+
+def test_uneven_and_tiny_instances(P):
+    import torch
+    _say("case: uneven tiny")
+    Ms = [5, 1, 2, 40, 3, 17]
+    batch = [G.make_instance("m144_k5", M=m, seed=m) for m in Ms]
+    # K = 1 for all (M = 1 allowed), then K = 2 without the M = 1 instance
+    b1 = _alloc(batch, 1, want_corr=False)
+    P.gbs_cumulants_batched(b1, 1, 0)
+    for (M, s, _, cum) in b1:
+        _, k1 = P.gbs_cumulants(M, s, 1, 0)
+        assert torch.equal(cum, k1)
+    b2 = _alloc([x for x in batch if x.M >= 2], 2)
+    P.gbs_cumulants_batched(b2, 2, 0)
+    for (M, s, corr, cum) in b2:
+        c1, k1 = P.gbs_cumulants(M, s, 2, 0)
+        assert torch.equal(corr, c1) and torch.equal(cum, k1)
+
+
+def test_autotune_and_set_tuning(P):
+    import torch
+    _say("case: autotune")
+    batch = G.make_batch(count=8, seed=5, m_range=(20, 60))
+    bufs = _alloc(batch, 3)
+    best = P.gbs_autotune_batched(bufs, 3, 0)
+    _say("autotuned", best)
+    assert best["block"] in (64, 128, 256) and best["unroll"] in (1, 2, 4)
+    assert best["tile"] % (best["block"] * best["unroll"]) == 0
+    P.gbs_cumulants_batched(bufs, 3, 0)
+    torch.cuda.synchronize()
+    ref = [(c.clone(), k.clone()) for (_, _, c, k) in bufs]
+    P.gbs_set_tuning(3, 0, {"block": 64, "unroll": 2, "tile": 128, "waves_per_cu": 1})
+    P.gbs_cumulants_batched(bufs, 3, 0)
+    torch.cuda.synchronize()
+    for (_, _, c, k), (c0, k0) in zip(bufs, ref):
+        assert torch.equal(c, c0) and torch.equal(k, k0)
+    with pytest.raises(P.GBSError):
+        P.gbs_set_tuning(3, 0, {"block": 96, "unroll": 1, "tile": 96, "waves_per_cu": 1})
+    P.gbs_set_tuning(3, 0, None)
+
+
+def test_batched_timing_entries(P):
+    import torch
+    _say("case: batched timing")
+    batch = G.make_batch(count=3, seed=9, m_range=(10, 20))
+    bufs = _alloc(batch, 3)
+    P.gbs_cumulants_batched(bufs, 3, P.GBS_TIMING)
+    torch.cuda.synchronize()
+    stages = [t[0] for t in P.gbs_last_timings()]
+    assert "batched" in stages and "build_q" in stages
+    for (M, s, corr, cum) in bufs:
+        c1, k1 = P.gbs_cumulants(M, s, 3, 0)
+        assert torch.equal(corr, c1) and torch.equal(cum, k1)
