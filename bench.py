@@ -155,11 +155,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="which form gives the headline value (both are measured)")
-    ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
-                    help="measure one form only (profiling runs)")
+    ap.add_argument("--only", choices=["fp64", "mixed", "fp64_all_minors", "mixed_all_minors"],
+                    default=None, help="measure one form only (profiling runs)")
+    ap.add_argument("--all-minors", action="store_true",
+                    help="also measure the all-minors kernel (GBS_ALL_MINORS) of both precisions")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device-to-device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the path needs no communication and every "
@@ -175,6 +179,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n}), flush=True)
+        return
     P.lib()
     inst = G.make_instance("m144_k5")
     sigma = torch.from_numpy(inst.sigma).to("cuda:0")
@@ -182,13 +195,19 @@ def main():
     log(f"[bench] M={M} K={K} outputs={N}")
 
     forms = [args.only] if args.only else ["fp64", "mixed"]
+    if args.all_minors and not args.only:
+        forms += ["fp64_all_minors", "mixed_all_minors"]
     res, bufs = {}, {}
     for form in forms:
         corr = torch.empty(N, dtype=torch.float64, device="cuda:0")
         cum = torch.empty(N, dtype=torch.float64, device="cuda:0")
-        flags = P.GBS_MIXED if form == "mixed" else 0
+        flags = (P.GBS_MIXED if form.startswith("mixed") else 0) | \
+            (P.GBS_ALL_MINORS if form.endswith("all_minors") else 0)
         res[form] = run_precision(P, torch, sigma, corr, cum, flags, args.steps, args.warmup, form)
-        bufs[form] = (corr, cum)
+        if form in ("fp64", "mixed"):
+            bufs[form] = (corr, cum)
+        else:
+            del corr, cum
 
     primary = args.precision if args.precision in res else forms[0]
     r = res[primary]

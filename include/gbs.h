@@ -73,8 +73,10 @@ enum {
                         inclusion-exclusion and partition sums (not for gbs_cumulant_grad)     */
     GBS_ASYNC = 4,   /* bit 2 set:   return right after the launches; a NOT_SPD pivot is then
                         reported only by gbs_last_error after the stream has completed          */
-    GBS_TIMING = 8   /* bit 3 set:   record a HIP event pair around every kernel launch of the
+    GBS_TIMING = 8,  /* bit 3 set:   record a HIP event pair around every kernel launch of the
                         call, on `stream`; read them back with gbs_last_timings               */
+    GBS_ALL_MINORS = 16 /* bit 4 set: evaluate all 2^d principal minors of every subset from Q
+                        (no lower-order tables): the kernel of the batched launch; slower    */
 };
 
 /* Kernel stages reported by gbs_last_timings. */
@@ -124,8 +126,11 @@ GBS_API gbs_status gbs_colex_unrank(int32_t d, int64_t r, int32_t* S);
 GBS_API gbs_status gbs_correlators(int32_t M, const double* sigma, int32_t max_order, int32_t flags,
                            double* corr, void* stream);
 
-/* Correlators and cumulants in one pass (the cumulant of each subset is formed
- * from the correlators of its sub-blocks, computed in the same thread).
+/* Correlators and cumulants.  Orders run in sequence; by default an order-d
+ * subset factors one new 2d x 2d block of Q and reads the vacuum probabilities,
+ * correlators and cumulants of its lower-order sub-blocks from the previous
+ * orders (App. B, Eq. correlators_expanded_2 for the cumulant); with
+ * GBS_ALL_MINORS it evaluates all of them itself.
  *   corr   device, N(M, K) FP64, or NULL to skip writing the correlators
  *   cum    device, N(M, K) FP64, overwritten with kappa~ (click) or kappa (parity)
  * Other arguments as gbs_correlators. */
@@ -157,8 +162,10 @@ typedef struct {
 } gbs_instance;
 
 /* Many instances of uneven M in one persistent launch (plus one launch that
- * forms every instance's Q).  Results equal n separate gbs_cumulants calls
- * bit for bit in GBS_FP64 mode.  The pipeline is captured once into a HIP
+ * forms every instance's Q).  Work items are independent, so every subset is
+ * evaluated by the all-minors arithmetic: results agree with n separate
+ * gbs_cumulants calls to FP64 rounding (the same arithmetic compiled into a
+ * different kernel may round its last bits differently).  The pipeline is captured once into a HIP
  * graph per (stream, instance list, order, flags) and replayed on later calls
  * with the same list; block shape and unroll come from gbs_autotune_batched's
  * cached choice when one exists for this device, else from a fixed default.

@@ -6,7 +6,7 @@ point names, the torch.autograd.Function wrapper, and the differentiable
 covariance model used to fit per-mode transmissions and squeezings.
 """
 from ._binding import (  # noqa: F401
-    EXPORTS, GBS_ASYNC, GBS_CLICK, GBS_E_DEVICE, GBS_E_INVALID_ARG, GBS_E_NOT_SPD,
+    EXPORTS, GBS_ALL_MINORS, GBS_ASYNC, GBS_CLICK, GBS_E_DEVICE, GBS_E_INVALID_ARG, GBS_E_NOT_SPD,
     GBS_E_OUT_OF_MEMORY, GBS_E_UNSUPPORTED, GBS_FP64, GBS_MAX_MODES, GBS_MAX_ORDER, GBS_MIXED,
     GBS_OK, GBS_PARITY, GBS_TIMING, GBSError, STAGE_NAMES, gbs_last_timings, LIB_PATH, gbs_autotune_batched, gbs_colex_rank,
     gbs_colex_unrank, gbs_correlators, gbs_cumulant_grad, gbs_cumulants, gbs_cumulants_batched,

@@ -10,7 +10,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgbs.so")
+# GBS_LIBRARY may name another build of the same library (same ABI)
+LIB_PATH = os.environ.get("GBS_LIBRARY") or os.path.join(_HERE, "libgbs.so")
 
 GBS_OK = 0
 GBS_E_INVALID_ARG = 1
@@ -25,6 +26,7 @@ GBS_FP64 = 0
 GBS_MIXED = 2
 GBS_ASYNC = 4
 GBS_TIMING = 8
+GBS_ALL_MINORS = 16
 
 GBS_STAGE_BUILD_Q = 0
 GBS_STAGE_NORMALISE = 1

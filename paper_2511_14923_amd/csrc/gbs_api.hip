@@ -1,7 +1,9 @@
 // C ABI of libgbs: argument checks, per-device context, scratch, launches.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "gbs.h"
@@ -116,13 +118,14 @@ gbs_status to_status(hipError_t e) {
 bool valid_problem(int32_t M, int32_t K, int32_t flags) {
   if (M < 1 || M > GBS_MAX_MODES) return false;
   if (K < 1 || K > GBS_MAX_ORDER || K > M) return false;
-  if (flags & ~(GBS_PARITY | GBS_MIXED | GBS_ASYNC | GBS_TIMING)) return false;
+  if (flags & ~(GBS_PARITY | GBS_MIXED | GBS_ASYNC | GBS_TIMING | GBS_ALL_MINORS)) return false;
   return true;
 }
 
 // Scratch layout of one forward call.
 struct ForwardScratch {
   double* Qi;
+  double* Qd;
   double* pk;
   float* E;
   DeviceStatus* st;
@@ -137,6 +140,8 @@ ForwardScratch layout_scratch(char* base, int M, bool mixed) {
   const size_t nq = 4 * (size_t)M * M;
   s.Qi = reinterpret_cast<double*>(base + off);
   off += align256(nq * sizeof(double));
+  s.Qd = reinterpret_cast<double*>(base + off);
+  off += align256(4 * (size_t)M * sizeof(double));
   if (mixed) {
     s.pk = reinterpret_cast<double*>(base + off);
     off += align256((size_t)M * sizeof(double));
@@ -210,29 +215,50 @@ gbs_status run_forward(int32_t M, const double* sigma, int32_t K, int32_t flags,
   DeviceContext* ctx = current_context(&e);
   if (!ctx) return to_status(e);
   const bool mixed = (flags & GBS_MIXED) != 0;
+  const bool rec = !(flags & GBS_ALL_MINORS);
   ForwardScratch probe = layout_scratch(nullptr, M, mixed);
+  // lower-order tables of the recursive kernel: p always, m when corr is NULL
+  const size_t nlow = K >= 2 ? (size_t)gbs_order_offset(M, K) : 0;
+  const size_t tab_bytes = rec ? align256(nlow * sizeof(double)) * (corr ? 1 : 2) : 0;
   void* scratch = nullptr;
-  e = hipMallocAsync(&scratch, probe.bytes, s);
+  e = hipMallocAsync(&scratch, probe.bytes + tab_bytes, s);
   if (e != hipSuccess) return to_status(e);
   ForwardScratch sc = layout_scratch(static_cast<char*>(scratch), M, mixed);
+  double* ptab = reinterpret_cast<double*>(static_cast<char*>(scratch) + probe.bytes);
+  double* mtab = corr ? corr : ptab + align256(nlow * sizeof(double)) / sizeof(double);
   t_err.order = 0;
   t_err.rank = -1;
   timing_start_call((flags & GBS_TIMING) != 0);
   e = launch_clear_status(sc.st, s);
   if (e == hipSuccess) e = timing_begin(s, GBS_STAGE_BUILD_Q, 0);
   if (e == hipSuccess) e = launch_build_q(sigma, M, sc.Qi, s);
+  if (e == hipSuccess) e = launch_build_qdiag(sc.Qi, M, sc.Qd, s);
   if (e == hipSuccess) e = timing_end(s);
   if (e == hipSuccess && mixed) {
     e = timing_begin(s, GBS_STAGE_NORMALISE, 0);
     if (e == hipSuccess) e = launch_build_normalised(sc.Qi, M, sc.pk, sc.E, s);
     if (e == hipSuccess) e = timing_end(s);
   }
+  const double* p_tab[kMaxOrder + 1] = {};
+  const double* m_tab[kMaxOrder + 1] = {};
+  const double* k_tab[kMaxOrder + 1] = {};
   for (int d = 1; d <= K && e == hipSuccess; ++d) {
     const int64_t off = gbs_order_offset(M, d);
     e = timing_begin(s, GBS_STAGE_FORWARD, d);
-    if (e == hipSuccess)
+    if (e != hipSuccess) break;
+    if (rec) {
+      double* m_out = (corr || d < K) ? mtab + off : nullptr;
+      double* k_out = cum ? cum + off : nullptr;
+      double* p_out = d < K ? ptab + off : nullptr;
+      e = launch_forward_rec(d, M, flags, sc.Qi, sc.Qd, sc.pk, sc.E, ctx->binom, p_tab, m_tab,
+                             k_tab, m_out, k_out, p_out, sc.st, s);
+      p_tab[d] = ptab + off;
+      m_tab[d] = mtab + off;
+      k_tab[d] = cum ? cum + off : nullptr;
+    } else {
       e = launch_forward(d, M, flags, sc.Qi, sc.pk, sc.E, ctx->binom, corr ? corr + off : nullptr,
                          cum ? cum + off : nullptr, nullptr, sc.st, s);
+    }
     if (e == hipSuccess) e = timing_end(s);
   }
   if (e != hipSuccess) {
@@ -252,6 +278,7 @@ gbs_status run_adjoint(int32_t M, const double* sigma, int32_t K, int32_t flags,
   const size_t nq = 4 * (size_t)M * M;
   size_t off = 0;
   const size_t oQ = off; off += align256(nq * sizeof(double));
+  const size_t oQd = off; off += align256(4 * (size_t)M * sizeof(double));
   const size_t oP = off; off += align256(N * sizeof(double));
   const size_t oM = off; off += align256(N * sizeof(double));
   const size_t oD = off; off += align256(N * sizeof(double));
@@ -263,6 +290,7 @@ gbs_status run_adjoint(int32_t M, const double* sigma, int32_t K, int32_t flags,
   if (e != hipSuccess) return to_status(e);
   char* b = static_cast<char*>(scratch);
   double* Qi = reinterpret_cast<double*>(b + oQ);
+  double* Qd = reinterpret_cast<double*>(b + oQd);
   double* ptab = reinterpret_cast<double*>(b + oP);
   double* m = reinterpret_cast<double*>(b + oM);
   double* d1 = reinterpret_cast<double*>(b + oD);
@@ -275,13 +303,19 @@ gbs_status run_adjoint(int32_t M, const double* sigma, int32_t K, int32_t flags,
   e = launch_clear_status(st, s);
   if (e == hipSuccess) e = timing_begin(s, GBS_STAGE_BUILD_Q, 0);
   if (e == hipSuccess) e = launch_build_q(sigma, M, Qi, s);
+  if (e == hipSuccess) e = launch_build_qdiag(Qi, M, Qd, s);
   if (e == hipSuccess) e = timing_end(s);
+  const double* p_tab[kMaxOrder + 1] = {};
+  const double* m_tab[kMaxOrder + 1] = {};
+  const double* k_tab[kMaxOrder + 1] = {};
   for (int d = 1; d <= K && e == hipSuccess; ++d) {
     const int64_t o = gbs_order_offset(M, d);
     e = timing_begin(s, GBS_STAGE_FORWARD, d);
     if (e == hipSuccess)
-      e = launch_forward(d, M, flags & GBS_PARITY, Qi, nullptr, nullptr, ctx->binom, m + o, nullptr,
-                         ptab + o, st, s);
+      e = launch_forward_rec(d, M, flags & GBS_PARITY, Qi, Qd, nullptr, nullptr, ctx->binom,
+                             p_tab, m_tab, k_tab, m + o, nullptr, ptab + o, st, s);
+    p_tab[d] = ptab + o;
+    m_tab[d] = m + o;
     if (e == hipSuccess) e = timing_end(s);
   }
   if (e == hipSuccess)

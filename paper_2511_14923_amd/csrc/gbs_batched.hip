@@ -381,7 +381,7 @@ gbs_status capture_plan(BatchPlan* p) {
 bool valid_batch(int n, const gbs_instance* inst, int K, int flags) {
   if (n < 1 || n > 4096 || !inst) return false;
   if (K < 1 || K > GBS_MAX_ORDER) return false;
-  if (flags & ~(GBS_PARITY | GBS_MIXED | GBS_ASYNC | GBS_TIMING)) return false;
+  if (flags & ~(GBS_PARITY | GBS_MIXED | GBS_ASYNC | GBS_TIMING | GBS_ALL_MINORS)) return false;
   for (int i = 0; i < n; ++i) {
     const gbs_instance& I = inst[i];
     if (I.M < K || I.M > GBS_MAX_MODES || I.reserved != 0 || !I.sigma || !I.cum) return false;
@@ -532,7 +532,8 @@ gbs_status gbs_autotune_batched(int32_t n, const gbs_instance* inst, int32_t max
 
 gbs_status gbs_set_tuning(int32_t max_order, int32_t flags, const gbs_tuning* t) {
   if (max_order < 1 || max_order > GBS_MAX_ORDER) return GBS_E_INVALID_ARG;
-  if (flags & ~(GBS_PARITY | GBS_MIXED | GBS_ASYNC | GBS_TIMING)) return GBS_E_INVALID_ARG;
+  if (flags & ~(GBS_PARITY | GBS_MIXED | GBS_ASYNC | GBS_TIMING | GBS_ALL_MINORS))
+    return GBS_E_INVALID_ARG;
   return set_tuning(max_order, flags, t);
 }
 

@@ -53,6 +53,35 @@ struct Tri {
   double a[tri_size(N)];
 };
 
+template <int N>
+struct TriF {
+  float a[tri_size(N)];
+};
+
+// Gather the normalised deviation F = E_S (FP32, zero diagonal blocks) for
+// modes s[0..n-1] in the given order.
+template <int n>
+__device__ __forceinline__ void gather_e(const float* __restrict__ E, int M, const int* s,
+                                         TriF<2 * n>& F) {
+  const size_t lde = 2 * (size_t)M;
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    F.a[tri(2 * i, 2 * i)] = 0.0f;
+    F.a[tri(2 * i + 1, 2 * i)] = 0.0f;
+    F.a[tri(2 * i + 1, 2 * i + 1)] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      const float* q = E + (size_t)(2 * s[i]) * lde + 2 * s[j];
+      const float2 q0 = *reinterpret_cast<const float2*>(q);
+      const float2 q1 = *reinterpret_cast<const float2*>(q + lde);
+      F.a[tri(2 * i, 2 * j)] = q0.x;
+      F.a[tri(2 * i, 2 * j + 1)] = q0.y;
+      F.a[tri(2 * i + 1, 2 * j)] = q1.x;
+      F.a[tri(2 * i + 1, 2 * j + 1)] = q1.y;
+    }
+  }
+}
+
 // Schur complement of the leading 2x2 block P of A (n x n, n >= 4):
 //   S = A_rr - A_r0 P^{-1} A_0r,  P^{-1} = adj(P) / det(P).
 // Returns det(P); inv_det = 1/det(P) is supplied by the caller (it usually
@@ -98,6 +127,82 @@ __device__ __forceinline__ void gather_q(const double* __restrict__ Qi, int M, c
   }
 }
 
+// As gather_q, for a block order in which block V's mode varies fastest across
+// the lanes of a wavefront (consecutive colex ranks differ in their smallest
+// mode): the blocks in V's block row are read from the transposed position
+// (a row shared by the wavefront, consecutive columns) and V's diagonal block
+// from the per-mode table Qd (x-x, p-x, p-p entries, 4 doubles per mode), so
+// every load instruction is coalesced or a broadcast.
+template <int n, int V>
+__device__ __forceinline__ void gather_q_coalesced(const double* __restrict__ Qi,
+                                                   const double* __restrict__ Qd, int M,
+                                                   const int* s, Tri<2 * n>& A) {
+  const size_t ldq = 2 * (size_t)M;
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      if (i == V && j == V) {
+        const double2 d0 = *reinterpret_cast<const double2*>(Qd + 4 * (size_t)s[i]);
+        const double2 d1 = *reinterpret_cast<const double2*>(Qd + 4 * (size_t)s[i] + 2);
+        A.a[tri(2 * i, 2 * i)] = d0.x;
+        A.a[tri(2 * i + 1, 2 * i)] = d0.y;
+        A.a[tri(2 * i + 1, 2 * i + 1)] = d1.x;
+      } else if (i == V) {
+        // block (V, j) = transpose of block (j, V)
+        const double* q = Qi + (size_t)(2 * s[j]) * ldq + 2 * s[i];
+        const double2 q0 = *reinterpret_cast<const double2*>(q);        // (j_x, V_x), (j_x, V_p)
+        const double2 q1 = *reinterpret_cast<const double2*>(q + ldq);  // (j_p, V_x), (j_p, V_p)
+        A.a[tri(2 * i, 2 * j)] = q0.x;
+        A.a[tri(2 * i + 1, 2 * j)] = q0.y;
+        A.a[tri(2 * i, 2 * j + 1)] = q1.x;
+        A.a[tri(2 * i + 1, 2 * j + 1)] = q1.y;
+      } else {
+        const double* q = Qi + (size_t)(2 * s[i]) * ldq + 2 * s[j];
+        const double2 q0 = *reinterpret_cast<const double2*>(q);
+        const double2 q1 = *reinterpret_cast<const double2*>(q + ldq);
+        A.a[tri(2 * i, 2 * j)] = q0.x;
+        A.a[tri(2 * i + 1, 2 * j)] = q1.x;
+        A.a[tri(2 * i + 1, 2 * j + 1)] = q1.y;
+        if (i != j) A.a[tri(2 * i, 2 * j + 1)] = q0.y;
+      }
+    }
+  }
+}
+
+// The same for the normalised FP32 deviation E (symmetric, zero diagonal blocks).
+template <int n, int V>
+__device__ __forceinline__ void gather_e_coalesced(const float* __restrict__ E, int M, const int* s,
+                                                   TriF<2 * n>& F) {
+  const size_t lde = 2 * (size_t)M;
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    F.a[tri(2 * i, 2 * i)] = 0.0f;
+    F.a[tri(2 * i + 1, 2 * i)] = 0.0f;
+    F.a[tri(2 * i + 1, 2 * i + 1)] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      if (i == V) {
+        const float* q = E + (size_t)(2 * s[j]) * lde + 2 * s[i];
+        const float2 q0 = *reinterpret_cast<const float2*>(q);
+        const float2 q1 = *reinterpret_cast<const float2*>(q + lde);
+        F.a[tri(2 * i, 2 * j)] = q0.x;
+        F.a[tri(2 * i + 1, 2 * j)] = q0.y;
+        F.a[tri(2 * i, 2 * j + 1)] = q1.x;
+        F.a[tri(2 * i + 1, 2 * j + 1)] = q1.y;
+      } else {
+        const float* q = E + (size_t)(2 * s[i]) * lde + 2 * s[j];
+        const float2 q0 = *reinterpret_cast<const float2*>(q);
+        const float2 q1 = *reinterpret_cast<const float2*>(q + lde);
+        F.a[tri(2 * i, 2 * j)] = q0.x;
+        F.a[tri(2 * i, 2 * j + 1)] = q0.y;
+        F.a[tri(2 * i + 1, 2 * j)] = q1.x;
+        F.a[tri(2 * i + 1, 2 * j + 1)] = q1.y;
+      }
+    }
+  }
+}
+
 // Colex unranking.  bin[k * ld + n] = C(n, k) for k = 1..D, n = 0..M.
 // Writes s[0] < s[1] < ... < s[D-1] with sum_j C(s[j], j+1) = r.
 template <int D, typename Table>
@@ -117,6 +222,56 @@ __device__ __forceinline__ void colex_unrank(uint64_t r, int M, const Table* bin
     r -= (uint64_t)col[lo];
     hi = lo;
   }
+}
+
+// Colex unranking by estimate and correction.  At level j the element is the
+// largest x < hi with C(x, j) <= r; since C(x, j) ~ (x - (j-1)/2)^j / j!, the
+// estimate x ~ (j! r)^(1/j) + (j-1)/2 (FP32) is within a step or two, and exact
+// integer comparisons against the binomial table finish the search.
+// col_j(x) = bin[j * ld + x] = C(x, j).
+template <int D, typename Tab>
+__device__ __forceinline__ void colex_unrank_est(uint64_t r, int M, const Tab* bin, int ld,
+                                                 int (&s)[D]) {
+  constexpr float kFact[6] = {1.f, 1.f, 2.f, 6.f, 24.f, 120.f};
+  int hi = M;
+#pragma unroll
+  for (int j = D; j >= 1; --j) {
+    const Tab* col = bin + j * ld;
+    int x;
+    if (j == 1) {
+      x = (int)r;
+    } else {
+      const float fr = (float)r;
+      float est;
+      if (j == 2) {
+        est = 0.5f * (1.0f + __builtin_amdgcn_sqrtf(fmaf(8.0f, fr, 1.0f)));
+      } else {
+        const float lg = __builtin_amdgcn_logf(fr * kFact[j]) * (1.0f / (float)j);
+        est = __builtin_amdgcn_exp2f(lg) + 0.5f * (float)(j - 1);
+      }
+      x = (int)est;
+      x = x < j - 1 ? j - 1 : (x > hi - 1 ? hi - 1 : x);
+      while (x + 1 < hi && (uint64_t)col[x + 1] <= r) ++x;
+      while (x > j - 1 && (uint64_t)col[x] > r) --x;
+    }
+    s[j - 1] = x;
+    r -= (uint64_t)col[x];
+    hi = x;
+  }
+}
+
+// Load from a uniform base pointer at a 32-bit element index (byte offset < 2^32).
+__device__ __forceinline__ double load_at(const double* __restrict__ base, uint32_t idx) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + (idx << 3));
+}
+__device__ __forceinline__ double load_at(const double* __restrict__ base, uint64_t idx) {
+  return base[idx];
+}
+__device__ __forceinline__ void store_at(double* __restrict__ base, uint32_t idx, double v) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (idx << 3)) = v;
+}
+__device__ __forceinline__ void store_at(double* __restrict__ base, uint64_t idx, double v) {
+  base[idx] = v;
 }
 
 }  // namespace gbs

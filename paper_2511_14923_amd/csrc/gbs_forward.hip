@@ -82,6 +82,23 @@ __global__ void build_q_kernel(const double* __restrict__ sigma, int M, double* 
   }
 }
 
+// Per-mode diagonal blocks of Q (x-x, p-x, p-p, 0) for coalesced access by mode.
+__global__ void build_qdiag_kernel(const double* __restrict__ Qi, int M, double* __restrict__ Qd) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const size_t ldq = 2 * (size_t)M;
+  const double* q = Qi + (size_t)(2 * k) * ldq + 2 * k;
+  Qd[4 * (size_t)k + 0] = q[0];
+  Qd[4 * (size_t)k + 1] = q[ldq];
+  Qd[4 * (size_t)k + 2] = q[ldq + 1];
+  Qd[4 * (size_t)k + 3] = 0.0;
+}
+
+hipError_t launch_build_qdiag(const double* Qi, int M, double* Qd, hipStream_t s) {
+  hipLaunchKernelGGL(build_qdiag_kernel, dim3((M + 255) / 256), dim3(256), 0, s, Qi, M, Qd);
+  return hipGetLastError();
+}
+
 __global__ void clear_status_kernel(DeviceStatus* st) {
   st->flag = 0;
   st->order = 0;

@@ -1,0 +1,368 @@
+// Order-recursive forward kernel: one new determinant per subset, everything
+// else read from the tables of the lower orders.
+//
+// Orders run in sequence (1, 2, ..., K); order d reads the vacuum
+// probabilities p, correlators m and cumulants k that orders 1..d-1 stored.
+// For a subset S = {a} + B with a its smallest mode, e its largest and
+// B' = B \ {e}, the thread
+//   1. factors Q_S in block order [B', a, e] (2x2 pivots, one reciprocal square
+//      root each); the last two leading minors are p(S \ {e}) and p(S)
+//      (p(T) = det(Q_T)^(-1/2), App. D.1, Eq. vacuum_gaussian_prob);
+//   2. reads p({a} + U) for the other subsets U of B, m(W) for W subset of B,
+//      and k(R + {e}) for the proper subsets R of {a} + B';
+//   3. forms nu(W) = sum_{U subset W} s_|U| p({a} + U) for every W subset of B by a
+//      subset zeta transform (s_t = (-1)^t click, (-2)^t parity), then
+//        click   mu(W + a) = mu(W) - nu(W)
+//        parity  c(W + a)  = -c(W) + 2 (-1)^|W| nu(W)
+//      (both split the inclusion-exclusion of App. D.1 / Eq. corre_cov_main
+//      into the terms without and with mode a; m(empty) = 1);
+//   4. forms the cumulant by the fixed-element recursion on e
+//        k(S) = m(S) - sum_{R proper subset of {a}+B'} k(R + {e}) m({a} + B' \ R)
+//      (the partition sum of Eq. cumulant_corr_main grouped by the block that
+//      contains e; App. B, Eq. correlators_expanded_2);
+//   5. stores m(S), k(S) and, below the last order, p(S).
+// Every distinct principal minor of Q is thus factored once per subset that
+// ends with it, and every output costs one 2d x 2d factorisation plus
+// O(2^d) additions -- the work count of the method's cost model.
+#include <hip/hip_runtime.h>
+
+#include "gbs_internal.h"
+
+namespace gbs {
+
+struct OrderTables {
+  const double* p[kMaxOrder + 1];  // p[d]: order-d vacuum probabilities (d < current)
+  const double* m[kMaxOrder + 1];  // order-d correlators
+  const double* k[kMaxOrder + 1];  // order-d cumulants
+};
+
+// Leading-block elimination chain: multiplies P by det(pivot)^(-1/2) for each
+// of the N/2 blocks; pA receives the product after block N/2 - 2 (all but the
+// last block).
+template <int n, int NB>
+__device__ __forceinline__ void chain(const Tri<n>& A, double P, double& pA, double& pS, bool& bad) {
+  const double a00 = A.a[0], a10 = A.a[1], a11 = A.a[2];
+  const double det = fma(a00, a11, -a10 * a10);
+  bad |= !(a00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
+  const double y = rsqrt_f64(det);
+  const double Pn = P * y;
+  if constexpr (n == 2) {
+    pS = Pn;
+  } else {
+    if constexpr (n == 4) pA = Pn;
+    Tri<n - 2> S;
+    schur_leading_block<n>(A, y * y, S);
+    chain<n - 2, NB>(S, Pn, pA, pS, bad);
+  }
+}
+
+// FP32 chain on the deviation F = A - I of the normalised matrix (unit
+// diagonal blocks): every pivot contributes delta = det(I + F00) - 1 and the
+// factor (1 + delta)^(-1/2) = 1 + eta with eta = -delta y^2 / (1 + y); the
+// deviations compose as rho' = rho + eta + rho eta.  rhoA is the deviation
+// after all but the last block, rhoS after all blocks.
+template <int n>
+__device__ __forceinline__ void chain_dev(const TriF<n>& F, float rho, float& rhoA, float& rhoS,
+                                          bool& bad) {
+  const float f00 = F.a[0], f10 = F.a[1], f11 = F.a[2];
+  const float delta = f00 + f11 + fmaf(f00, f11, -f10 * f10);
+  const float onep = 1.0f + delta;
+  bad |= !(onep > 0.0f) || !(1.0f + f00 > 0.0f) || !(onep < INFINITY);
+  const float y = __builtin_amdgcn_rsqf(onep);
+  const float inv = y * y;
+  const float eta = -delta * inv * __builtin_amdgcn_rcpf(1.0f + y);
+  const float rn = rho + fmaf(rho, eta, eta);
+  if constexpr (n == 2) {
+    rhoS = rn;
+  } else {
+    if constexpr (n == 4) rhoA = rn;
+    const float g00 = 1.0f + f00, g11 = 1.0f + f11;
+    float u0[n], u1[n];
+#pragma unroll
+    for (int i = 2; i < n; ++i) {
+      const float c0 = F.a[tri(i, 0)], c1 = F.a[tri(i, 1)];
+      u0[i] = fmaf(g11, c0, -f10 * c1) * inv;
+      u1[i] = fmaf(g00, c1, -f10 * c0) * inv;
+    }
+    TriF<n - 2> S;
+#pragma unroll
+    for (int i = 2; i < n; ++i)
+#pragma unroll
+      for (int j = 2; j <= i; ++j)
+        S.a[tri(i - 2, j - 2)] =
+            fmaf(-F.a[tri(i, 1)], u1[j], fmaf(-F.a[tri(i, 0)], u0[j], F.a[tri(i, j)]));
+    chain_dev<n - 2>(S, rn, rhoA, rhoS, bad);
+  }
+}
+
+template <int D, int CONV, bool WANT_CUM, bool LDS_BIN, typename Idx, bool MIXED>
+__global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restrict__ Qi,
+                                                          const double* __restrict__ Qd,
+                                                          const double* __restrict__ pk,
+                                                          const float* __restrict__ E, int M,
+                                                          uint64_t count,
+                                                          const uint64_t* __restrict__ binom,
+                                                          OrderTables tab,
+                                                          double* __restrict__ m_out,
+                                                          double* __restrict__ k_out,
+                                                          double* __restrict__ p_out,
+                                                          DeviceStatus* __restrict__ st) {
+  static_assert(D >= 2 && D <= kMaxOrder, "orders 2..5");
+  constexpr int NB = D - 1;          // |B|
+  constexpr int NU = 1 << NB;        // subsets of B
+  constexpr int FULL = NU - 1;       // B
+  constexpr int FULLP = (1 << (NB - 1)) - 1;  // B' = B \ {e}
+  // binomial table C(n, k), k <= D, n <= M: in LDS (as Idx) when it fits
+  extern __shared__ uint64_t sbin_raw[];
+  const Idx* bin;
+  const uint64_t* gbin = binom;
+  int ld;
+  if constexpr (LDS_BIN) {
+    Idx* sb = reinterpret_cast<Idx*>(sbin_raw);
+    ld = M + 1;
+    for (int i = threadIdx.x; i < (D + 1) * ld; i += blockDim.x) {
+      const int kk = i / ld, nn = i - kk * ld;
+      sb[i] = (Idx)binom[kk * kBinLd + nn];
+    }
+    __syncthreads();
+    bin = sb;
+  } else {
+    ld = kBinLd;
+    bin = nullptr;
+  }
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < count; r += stride) {
+    int s[D];
+    if constexpr (LDS_BIN) colex_unrank_est<D>(r, M, bin, ld, s);
+    else colex_unrank_est<D>(r, M, gbin, ld, s);
+    const int a = s[0], e = s[D - 1];
+
+    // 1. factorisation in block order [s_1 .. s_{D-2}, a, e]
+    int ch[D];
+#pragma unroll
+    for (int i = 0; i < D - 2; ++i) ch[i] = s[i + 1];
+    ch[D - 2] = a;
+    ch[D - 1] = e;
+    double pA = 1.0, pS = 1.0;
+    bool bad = false;
+    if constexpr (MIXED) {
+      TriF<2 * D> F;
+      gather_e_coalesced<D, D - 2>(E, M, ch, F);
+      float rhoA = 0.0f, rhoS = 0.0f;
+      chain_dev<2 * D>(F, 0.0f, rhoA, rhoS, bad);
+      double PA = pk[a];
+#pragma unroll
+      for (int i = 1; i < D - 1; ++i) PA *= pk[s[i]];
+      const double PS = PA * pk[e];
+      pA = fma(PA, (double)rhoA, PA);
+      pS = fma(PS, (double)rhoS, PS);
+    } else {
+      Tri<2 * D> A;
+      gather_q_coalesced<D, D - 2>(Qi, Qd, M, ch, A);
+      chain<2 * D, D>(A, 1.0, pA, pS, bad);
+    }
+    if (bad) latch_failure(st, D, (int64_t)r);
+
+    // binomials C(s_i, k) for the rank arithmetic
+    Idx cb[D][D + 1];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int kk = 1; kk <= D; ++kk)
+        cb[i][kk] = LDS_BIN ? (Idx)bin[kk * ld + s[i]] : (Idx)gbin[kk * ld + s[i]];
+
+    // 2a. p({a} + U), U subset of B (B bit i <-> s[i+1])
+    double pu[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      if (u == FULL) {
+        pu[u] = pS;
+      } else if (u == FULLP) {
+        pu[u] = pA;
+      } else {
+        Idx rk = (Idx)a;  // C(a, 1)
+        int j = 0;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          if (u & (1 << i)) rk += cb[i + 1][(j++) + 2];
+        pu[u] = load_at(tab.p[popcount_c((unsigned)u) + 1], rk);
+      }
+    }
+    // 2b. m(W), W subset of B
+    double mw[NU];
+    mw[0] = 1.0;
+#pragma unroll
+    for (int w = 1; w < NU; ++w) {
+      Idx rk = 0;
+      int j = 0;
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (w & (1 << i)) rk += cb[i + 1][(j++) + 1];
+      mw[w] = load_at(tab.m[popcount_c((unsigned)w)], rk);
+    }
+
+    // 3. nu(W) by the zeta transform, then m(W + a)
+    double nu[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int t = popcount_c((unsigned)u);
+      if (CONV == GBS_CLICK) nu[u] = (t & 1) ? -pu[u] : pu[u];
+      else nu[u] = ((t & 1) ? -1.0 : 1.0) * (double)(1 << t) * pu[u];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+        if (u & (1 << b)) nu[u] += nu[u ^ (1 << b)];
+    double ma[NU];
+#pragma unroll
+    for (int w = 0; w < NU; ++w) {
+      if (CONV == GBS_CLICK) ma[w] = mw[w] - nu[w];
+      else ma[w] = fma((popcount_c((unsigned)w) & 1) ? -2.0 : 2.0, nu[w], -mw[w]);
+    }
+    const double mS = ma[FULL];
+    const Idx ri = (Idx)r;
+    if (m_out) store_at(m_out, ri, mS);
+    if (p_out) store_at(p_out, ri, pS);
+
+    // 4. cumulant by the fixed-element recursion on e.
+    // X = {a} + B': X bit 0 <-> a, X bit i <-> s[i] (i = 1..D-2).
+    if constexpr (WANT_CUM) {
+      constexpr int NX = 1 << (D - 1);
+      constexpr int FULLX = NX - 1;
+      double kS = mS;
+      double kc = 0.0;  // Neumaier compensation (mixed form)
+#pragma unroll
+      for (int R = 0; R < FULLX; ++R) {
+        // k(R + {e})
+        Idx rk = 0;
+        int j = 0;
+#pragma unroll
+        for (int i = 0; i < D - 1; ++i)
+          if (R & (1 << i)) rk += cb[i][(j++) + 1];
+        rk += cb[D - 1][j + 1];
+        const double kre = load_at(tab.k[j + 1], rk);
+        // m(X \ R)
+        const int Y = FULLX ^ R;
+        const double my = (Y & 1) ? ma[Y >> 1] : mw[Y >> 1];
+        if constexpr (MIXED) {
+          const double term = -kre * my;
+          const double t = kS + term;
+          kc += (fabs(kS) >= fabs(term)) ? ((kS - t) + term) : ((term - t) + kS);
+          kS = t;
+        } else {
+          kS = fma(-kre, my, kS);
+        }
+      }
+      store_at(k_out, ri, kS + kc);
+    }
+  }
+}
+
+// Order 1: p({a}) = det(Q_aa)^(-1/2), mu = 1 - p (click) or c = 2p - 1 (parity),
+// and the cumulant of a single mode is its correlator.
+template <int CONV>
+__global__ void forward_order1_kernel(const double* __restrict__ Qi, int M, double* __restrict__ m_out,
+                                      double* __restrict__ k_out, double* __restrict__ p_out,
+                                      DeviceStatus* __restrict__ st) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= M) return;
+  const size_t ldq = 2 * (size_t)M;
+  const double* q = Qi + (size_t)(2 * a) * ldq + 2 * a;
+  const double a00 = q[0], a10 = q[ldq], a11 = q[ldq + 1];
+  const double det = fma(a00, a11, -a10 * a10);
+  if (!(a00 > 0.0) || !(det > 0.0) || !(det < INFINITY)) latch_failure(st, 1, a);
+  const double p = rsqrt_f64(det);
+  const double m = (CONV == GBS_CLICK) ? 1.0 - p : fma(2.0, p, -1.0);
+  if (m_out) m_out[a] = m;
+  if (k_out) k_out[a] = m;
+  if (p_out) p_out[a] = p;
+}
+
+template <int D, int CONV, bool WC, typename Idx, bool MX>
+static hipError_t launch_rec_t(int M, const double* Qi, const double* Qd, const double* pk,
+                               const float* E,
+                               const uint64_t* binom, const OrderTables& tab, double* m_out,
+                               double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
+  const uint64_t count = host_binom(M, D);
+  if (count == 0) return hipSuccess;
+  const int block = 256;
+  const uint64_t grid = std::min<uint64_t>((count + block - 1) / block, kMaxGrid);
+  const size_t lds = (size_t)(D + 1) * (M + 1) * sizeof(Idx);
+  if (lds <= 48 * 1024) {
+    hipLaunchKernelGGL((forward_rec_kernel<D, CONV, WC, true, Idx, MX>), dim3((unsigned)grid),
+                       dim3(block), lds, s, Qi, Qd, pk, E, M, count, binom, tab, m_out, k_out, p_out, st);
+  } else {
+    hipLaunchKernelGGL((forward_rec_kernel<D, CONV, WC, false, Idx, MX>), dim3((unsigned)grid),
+                       dim3(block), 0, s, Qi, Qd, pk, E, M, count, binom, tab, m_out, k_out, p_out, st);
+  }
+  return hipGetLastError();
+}
+
+template <int D, int CONV, bool MX>
+static hipError_t launch_rec_w(int M, const double* Qi, const double* Qd, const double* pk,
+                               const float* E,
+                               const uint64_t* binom, const OrderTables& tab, double* m_out,
+                               double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
+  // 32-bit rank and byte-offset arithmetic when every table of orders <= D
+  // has fewer than 2^29 entries
+  bool small = true;
+  for (int d = 1; d <= D; ++d) small = small && host_binom(M, d) < (1ull << 29);
+  if (k_out) {
+    if (small)
+      return launch_rec_t<D, CONV, true, uint32_t, MX>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+    return launch_rec_t<D, CONV, true, uint64_t, MX>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+  }
+  if (small)
+    return launch_rec_t<D, CONV, false, uint32_t, MX>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+  return launch_rec_t<D, CONV, false, uint64_t, MX>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+}
+
+template <int D>
+static hipError_t launch_rec_c(int M, int flags, const double* Qi, const double* Qd,
+                               const double* pk,
+                               const float* E, const uint64_t* binom, const OrderTables& tab,
+                               double* m_out, double* k_out, double* p_out, DeviceStatus* st,
+                               hipStream_t s) {
+  const bool mx = (flags & GBS_MIXED) != 0;
+  if (flags & GBS_PARITY) {
+    if (mx) return launch_rec_w<D, GBS_PARITY, true>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+    return launch_rec_w<D, GBS_PARITY, false>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+  }
+  if (mx) return launch_rec_w<D, GBS_CLICK, true>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+  return launch_rec_w<D, GBS_CLICK, false>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+}
+
+hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const double* Qd,
+                              const double* pk,
+                              const float* E, const uint64_t* binom, const double* const* p_tab,
+                              const double* const* m_tab, const double* const* k_tab,
+                              double* m_out, double* k_out, double* p_out, DeviceStatus* st,
+                              hipStream_t s) {
+  OrderTables tab{};
+  for (int q = 1; q <= kMaxOrder; ++q) {
+    tab.p[q] = p_tab[q];
+    tab.m[q] = m_tab[q];
+    tab.k[q] = k_tab[q];
+  }
+  if (d == 1) {
+    const int block = 256;
+    const int grid = (M + block - 1) / block;
+    if (flags & GBS_PARITY)
+      hipLaunchKernelGGL(forward_order1_kernel<GBS_PARITY>, dim3(grid), dim3(block), 0, s, Qi, M,
+                         m_out, k_out, p_out, st);
+    else
+      hipLaunchKernelGGL(forward_order1_kernel<GBS_CLICK>, dim3(grid), dim3(block), 0, s, Qi, M,
+                         m_out, k_out, p_out, st);
+    return hipGetLastError();
+  }
+  switch (d) {
+    case 2: return launch_rec_c<2>(M, flags, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+    case 3: return launch_rec_c<3>(M, flags, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+    case 4: return launch_rec_c<4>(M, flags, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+    case 5: return launch_rec_c<5>(M, flags, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace gbs

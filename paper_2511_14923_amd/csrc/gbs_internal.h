@@ -29,6 +29,9 @@ DeviceContext* current_context(hipError_t* err);
 // 2M x 2M FP64, built from sigma's lower triangle.
 hipError_t launch_build_q(const double* sigma, int M, double* Qi, hipStream_t s);
 
+// Per-mode diagonal blocks of Q, 4 doubles per mode (x-x, p-x, p-p, 0).
+hipError_t launch_build_qdiag(const double* Qi, int M, double* Qd, hipStream_t s);
+
 // Mixed-precision operands: per-mode block Cholesky factors of Q, the
 // single-mode vacuum probabilities pk (FP64) and the normalised off-diagonal
 // blocks E = L_k^{-1} Q_kl L_l^{-T} (FP32, interleaved 2M x 2M, zero diagonal blocks).
@@ -53,6 +56,17 @@ hipError_t launch_clear_status(DeviceStatus* st, hipStream_t s);
 hipError_t launch_forward(int d, int M, int flags, const double* Qi, const double* pk,
                           const float* E, const uint64_t* binom, double* corr, double* cum,
                           double* ptab, DeviceStatus* st, hipStream_t s);
+
+// Order-recursive FP64 forward pass of order d (see gbs_forward_rec.hip):
+// p_tab/m_tab/k_tab[q] point at the order-q blocks of the lower-order tables
+// (q < d); m_out, k_out, p_out at the order-d blocks (each may be null).
+// GBS_MIXED reads pk and E (normalised Q) instead of Qi.
+hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const double* Qd,
+                              const double* pk,
+                              const float* E, const uint64_t* binom, const double* const* p_tab,
+                              const double* const* m_tab, const double* const* k_tab,
+                              double* m_out, double* k_out, double* p_out, DeviceStatus* st,
+                              hipStream_t s);
 
 // Vector-Jacobian product given the forward correlators m and vacuum
 // probabilities ptab of every subset (orders 1..K); d1, mbar, pbar are scratch

@@ -96,11 +96,6 @@ __device__ __forceinline__ void subset_fp64(const double* __restrict__ Qi, int M
   else cum = 0.0;
 }
 
-template <int N>
-struct TriF {
-  float a[tri_size(N)];
-};
-
 struct Neumaier {
   double s = 0.0, c = 0.0;
   __device__ __forceinline__ void add(double x) {

@@ -120,7 +120,7 @@ def test_autograd_chain_to_eta_and_r(P, c_oracle):
     # (a) oracle
     loss_ref, gsig_ref = O.c_loss_grad(inst.sigma, 3, target)
     d_eta, d_r = O.covariance_param_grad(inst.U, inst.r, inst.eta, gsig_ref)
-    assert float(loss) == pytest.approx(loss_ref, rel=1e-10)
+    assert float(loss.detach()) == pytest.approx(loss_ref, rel=1e-10)
     assert _normwise(np.concatenate([g_eta, g_r]), np.concatenate([d_eta, d_r])) < 1e-9
     # (b) finite differences of the GPU forward
     rng = np.random.default_rng(7)
