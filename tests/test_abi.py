@@ -67,7 +67,7 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.gbs_cumulants(0, fake, 1, 0, None, fake, None) == P.GBS_E_INVALID_ARG
     assert lib.gbs_cumulants(4, fake, 5, 0, None, fake, None) == P.GBS_E_INVALID_ARG
     assert lib.gbs_cumulants(10, fake, 6, 0, None, fake, None) == P.GBS_E_INVALID_ARG
-    assert lib.gbs_cumulants(10, fake, 3, 16, None, fake, None) == P.GBS_E_INVALID_ARG
+    assert lib.gbs_cumulants(10, fake, 3, 32, None, fake, None) == P.GBS_E_INVALID_ARG
     assert lib.gbs_cumulants(10, None, 3, 0, None, fake, None) == P.GBS_E_INVALID_ARG
     assert lib.gbs_cumulants(10, fake, 3, 0, fake, None, None) == P.GBS_E_INVALID_ARG
     assert lib.gbs_correlators(2049, fake, 1, 0, fake, None) == P.GBS_E_INVALID_ARG
