@@ -3,42 +3,74 @@
 //
 // Orders run in sequence (1, 2, ..., K); order d reads the vacuum
 // probabilities p, correlators m and cumulants k that orders 1..d-1 stored.
-// For a subset S = {a} + B with a its smallest mode, e its largest and
-// B' = B \ {e}, the thread
-//   1. factors Q_S in block order [B', a, e] (2x2 pivots, one reciprocal square
-//      root each); the last two leading minors are p(S \ {e}) and p(S)
-//      (p(T) = det(Q_T)^(-1/2), App. D.1, Eq. vacuum_gaussian_prob);
-//   2. reads p({a} + U) for the other subsets U of B, m(W) for W subset of B,
-//      and k(R + {e}) for the proper subsets R of {a} + B';
+// For a subset S = {a} + B with a its smallest mode, e its largest, d its
+// second largest and B' = B \ {e}, the thread
+//   1. reads p({a} + U) for the subsets U of B that the factorisation below
+//      does not give, m(W) for the subsets W of B, and k(Y + {e}) for the
+//      subsets Y of B' (all issued first, so that the factorisation hides
+//      their latency);
+//   2. factors Q_S in block order [B' \ {d}, a, d, e] (2x2 pivots, one
+//      reciprocal square root each; p(T) = det(Q_T)^(-1/2), App. D.1, Eq.
+//      vacuum_gaussian_prob): its leading minors give p(S \ {d, e}),
+//      p(S \ {e}) and p(S), and the e block of the Schur complement taken after
+//      S \ {d, e} gives p(S \ {d}) with one more 2x2 determinant (the mixed
+//      form factors the normalised FP32 deviation in order [B', a, e]);
 //   3. forms nu(W) = sum_{U subset W} s_|U| p({a} + U) for every W subset of B by a
 //      subset zeta transform (s_t = (-1)^t click, (-2)^t parity), then
 //        click   mu(W + a) = mu(W) - nu(W)
 //        parity  c(W + a)  = -c(W) + 2 (-1)^|W| nu(W)
 //      (both split the inclusion-exclusion of App. D.1 / Eq. corre_cov_main
 //      into the terms without and with mode a; m(empty) = 1);
-//   4. forms the cumulant by the fixed-element recursion on e
-//        k(S) = m(S) - sum_{R proper subset of {a}+B'} k(R + {e}) m({a} + B' \ R)
+//   4. forms the cumulants k(Y + {e}) of the subsets Y of {a} + B' that contain
+//      a, in increasing order, by the fixed-element recursion on e
+//        k(Y + {e}) = m(Y + {e}) - sum_{R proper subset of Y} k(R + {e}) m(Y \ R)
 //      (the partition sum of Eq. cumulant_corr_main grouped by the block that
-//      contains e; App. B, Eq. correlators_expanded_2);
+//      contains e; App. B, Eq. correlators_expanded_2); Y = {a} + B' gives k(S);
 //   5. stores m(S), k(S) and, below the last order, p(S).
-// Every distinct principal minor of Q is thus factored once per subset that
-// ends with it, and every output costs one 2d x 2d factorisation plus
-// O(2^d) additions -- the work count of the method's cost model.
+// Every output thus costs one 2d x 2d factorisation plus O(2^d) additions --
+// the work count of the method's cost model.  A capped grid of workgroups
+// strides over the ranks, so each workgroup fills its LDS binomial table once.
 #include <hip/hip_runtime.h>
 
 #include "gbs_internal.h"
 
 namespace gbs {
 
-struct OrderTables {
-  const double* p[kMaxOrder + 1];  // p[d]: order-d vacuum probabilities (d < current)
-  const double* m[kMaxOrder + 1];  // order-d correlators
-  const double* k[kMaxOrder + 1];  // order-d cumulants
-};
+// Workgroups of a launch; each strides over many subsets.
+constexpr uint64_t kRecGrid = 4096;
 
-// Leading-block elimination chain: multiplies P by det(pivot)^(-1/2) for each
-// of the N/2 blocks; pA receives the product after block N/2 - 2 (all but the
-// last block).
+// Leading-block elimination chain for the block order [.., a, d, e]: multiplies
+// P by det(pivot)^(-1/2) for each block; pDE receives the product before d
+// (p(S \ {d, e})), pD the product times the e block of the Schur complement
+// at that point (p(S \ {d})), pA the product before e (p(S \ {e})), pS the
+// full product.
+template <int n>
+__device__ __forceinline__ void chain2(const Tri<n>& A, double P, double& pDE, double& pD,
+                                       double& pA, double& pS, bool& bad) {
+  if constexpr (n == 4) {
+    pDE = P;
+    // e block of the 4x4 Schur complement
+    const double e00 = A.a[tri(2, 2)], e10 = A.a[tri(3, 2)], e11 = A.a[tri(3, 3)];
+    const double dete = fma(e00, e11, -e10 * e10);
+    bad |= !(dete > 0.0);
+    pD = P * rsqrt_f64(dete);
+  }
+  const double a00 = A.a[0], a10 = A.a[1], a11 = A.a[2];
+  const double det = fma(a00, a11, -a10 * a10);
+  bad |= !(a00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
+  const double y = rsqrt_f64(det);
+  const double Pn = P * y;
+  if constexpr (n == 2) {
+    pS = Pn;
+  } else {
+    if constexpr (n == 4) pA = Pn;
+    Tri<n - 2> S;
+    schur_leading_block<n>(A, y * y, S);
+    chain2<n - 2>(S, Pn, pDE, pD, pA, pS, bad);
+  }
+}
+
+// The same for the block order [.., a, e]: pA = p(S \ {e}), pS = p(S).
 template <int n, int NB>
 __device__ __forceinline__ void chain(const Tri<n>& A, double P, double& pA, double& pS, bool& bad) {
   const double a00 = A.a[0], a10 = A.a[1], a11 = A.a[2];
@@ -136,16 +168,51 @@ __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restri
     if constexpr (LDS_BIN) colex_unrank_est<D>(r, M, bin, ld, s);
     else colex_unrank_est<D>(r, M, gbin, ld, s);
     const int a = s[0], e = s[D - 1];
-
-    // 1. factorisation in block order [s_1 .. s_{D-2}, a, e]
-    int ch[D];
+    constexpr bool PDROP = D >= 3 && !MIXED;
+    // binomials C(s_i, k) for the rank arithmetic
+    Idx cb[D][D + 1];
 #pragma unroll
-    for (int i = 0; i < D - 2; ++i) ch[i] = s[i + 1];
-    ch[D - 2] = a;
-    ch[D - 1] = e;
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int kk = 1; kk <= D; ++kk)
+        cb[i][kk] = LDS_BIN ? (Idx)bin[kk * ld + s[i]] : (Idx)gbin[kk * ld + s[i]];
+    constexpr int UDROP_D = (D >= 3) ? (FULL ^ (1 << (D - 3))) : -1;           // B minus d
+    constexpr int UDROP_DE = (D >= 3) ? (FULL ^ (1 << (D - 3)) ^ (1 << (D - 2))) : -1;  // B minus d, e
+    double pu[NU];
+    double mw[NU];
+    auto load_lookups = [&]() {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        if (u == FULL || u == FULLP) continue;
+        if (PDROP && (u == UDROP_D || u == UDROP_DE)) continue;
+        Idx rk = (Idx)a;
+        int j = 0;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          if (u & (1 << i)) rk += cb[i + 1][(j++) + 2];
+        pu[u] = load_at(tab.p[popcount_c((unsigned)u) + 1], rk);
+      }
+      mw[0] = 1.0;
+#pragma unroll
+      for (int w = 1; w < NU; ++w) {
+        Idx rk = 0;
+        int j = 0;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          if (w & (1 << i)) rk += cb[i + 1][(j++) + 1];
+        mw[w] = load_at(tab.m[popcount_c((unsigned)w)], rk);
+      }
+    };
+    load_lookups();  // issued before the factorisation, which hides their latency
+
     double pA = 1.0, pS = 1.0;
     bool bad = false;
     if constexpr (MIXED) {
+      int ch[D];
+#pragma unroll
+      for (int i = 0; i < D - 2; ++i) ch[i] = s[i + 1];
+      ch[D - 2] = a;
+      ch[D - 1] = e;
       TriF<2 * D> F;
       gather_e_coalesced<D, D - 2>(E, M, ch, F);
       float rhoA = 0.0f, rhoS = 0.0f;
@@ -156,50 +223,34 @@ __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restri
       const double PS = PA * pk[e];
       pA = fma(PA, (double)rhoA, PA);
       pS = fma(PS, (double)rhoS, PS);
+    } else if constexpr (PDROP) {
+      int ch[D];
+#pragma unroll
+      for (int i = 0; i < D - 3; ++i) ch[i] = s[i + 1];
+      ch[D - 3] = a;
+      ch[D - 2] = s[D - 2];
+      ch[D - 1] = e;
+      Tri<2 * D> A;
+      gather_q_coalesced<D, D - 3>(Qi, Qd, M, ch, A);
+      double pDE = 1.0, pD = 1.0;
+      chain2<2 * D>(A, 1.0, pDE, pD, pA, pS, bad);
+      if constexpr (UDROP_D >= 0) {
+        pu[UDROP_D] = pD;
+        pu[UDROP_DE] = pDE;
+      }
     } else {
+      int ch[D];
+#pragma unroll
+      for (int i = 0; i < D - 2; ++i) ch[i] = s[i + 1];
+      ch[D - 2] = a;
+      ch[D - 1] = e;
       Tri<2 * D> A;
       gather_q_coalesced<D, D - 2>(Qi, Qd, M, ch, A);
       chain<2 * D, D>(A, 1.0, pA, pS, bad);
     }
     if (bad) latch_failure(st, D, (int64_t)r);
-
-    // binomials C(s_i, k) for the rank arithmetic
-    Idx cb[D][D + 1];
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-      for (int kk = 1; kk <= D; ++kk)
-        cb[i][kk] = LDS_BIN ? (Idx)bin[kk * ld + s[i]] : (Idx)gbin[kk * ld + s[i]];
-
-    // 2a. p({a} + U), U subset of B (B bit i <-> s[i+1])
-    double pu[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      if (u == FULL) {
-        pu[u] = pS;
-      } else if (u == FULLP) {
-        pu[u] = pA;
-      } else {
-        Idx rk = (Idx)a;  // C(a, 1)
-        int j = 0;
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-          if (u & (1 << i)) rk += cb[i + 1][(j++) + 2];
-        pu[u] = load_at(tab.p[popcount_c((unsigned)u) + 1], rk);
-      }
-    }
-    // 2b. m(W), W subset of B
-    double mw[NU];
-    mw[0] = 1.0;
-#pragma unroll
-    for (int w = 1; w < NU; ++w) {
-      Idx rk = 0;
-      int j = 0;
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-        if (w & (1 << i)) rk += cb[i + 1][(j++) + 1];
-      mw[w] = load_at(tab.m[popcount_c((unsigned)w)], rk);
-    }
+    pu[FULL] = pS;
+    pu[FULLP] = pA;
 
     // 3. nu(W) by the zeta transform, then m(W + a)
     double nu[NU];
@@ -225,36 +276,54 @@ __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restri
     if (m_out) store_at(m_out, ri, mS);
     if (p_out) store_at(p_out, ri, pS);
 
-    // 4. cumulant by the fixed-element recursion on e.
-    // X = {a} + B': X bit 0 <-> a, X bit i <-> s[i] (i = 1..D-2).
     if constexpr (WANT_CUM) {
       constexpr int NX = 1 << (D - 1);
       constexpr int FULLX = NX - 1;
-      double kS = mS;
-      double kc = 0.0;  // Neumaier compensation (mixed form)
+      constexpr int EBIT = 1 << (D - 2);  // e as a B bit
+      // K(Y) = k(Y + {e}) for Y subset of X = {a} + B' (X bit 0 <-> a, bit i <-> s[i])
+      double Kv[NX];
 #pragma unroll
-      for (int R = 0; R < FULLX; ++R) {
-        // k(R + {e})
-        Idx rk = 0;
-        int j = 0;
+      for (int Y = 0; Y < NX; ++Y) {
+        const bool has_a = Y & 1;
+        if (!has_a) {
+          if (Y == FULLX) continue;
+          Idx rk = 0;
+          int j = 0;
 #pragma unroll
-        for (int i = 0; i < D - 1; ++i)
-          if (R & (1 << i)) rk += cb[i][(j++) + 1];
-        rk += cb[D - 1][j + 1];
-        const double kre = load_at(tab.k[j + 1], rk);
-        // m(X \ R)
-        const int Y = FULLX ^ R;
-        const double my = (Y & 1) ? ma[Y >> 1] : mw[Y >> 1];
-        if constexpr (MIXED) {
-          const double term = -kre * my;
-          const double t = kS + term;
-          kc += (fabs(kS) >= fabs(term)) ? ((kS - t) + term) : ((term - t) + kS);
-          kS = t;
-        } else {
-          kS = fma(-kre, my, kS);
+          for (int i = 0; i < D - 1; ++i)
+            if (Y & (1 << i)) rk += cb[i][(j++) + 1];
+          rk += cb[D - 1][j + 1];
+          Kv[Y] = load_at(tab.k[j + 1], rk);
         }
       }
-      store_at(k_out, ri, kS + kc);
+      auto mu_of = [&](int Y) -> double {  // m(Y), Y subset of X
+        return (Y & 1) ? ma[Y >> 1] : mw[Y >> 1];
+      };
+      auto mu_e = [&](int Y) -> double {   // m(Y + {e})
+        const int W = (Y >> 1) | EBIT;
+        return (Y & 1) ? ma[W] : mw[W];
+      };
+      double kS = 0.0;
+#pragma unroll
+      for (int Y = 1; Y < NX; Y += 2) {  // Y contains a
+        double v = mu_e(Y);
+        double c = 0.0;
+#pragma unroll
+        for (int R = 0; R < Y; ++R) {
+          if ((R & Y) != R) continue;
+          if constexpr (MIXED) {
+            const double term = -Kv[R] * mu_of(Y ^ R);
+            const double t = v + term;
+            c += (fabs(v) >= fabs(term)) ? ((v - t) + term) : ((term - t) + v);
+            v = t;
+          } else {
+            v = fma(-Kv[R], mu_of(Y ^ R), v);
+          }
+        }
+        Kv[Y] = v + c;
+        if (Y == FULLX) kS = v + c;
+      }
+      store_at(k_out, ri, kS);
     }
   }
 }
@@ -287,7 +356,7 @@ static hipError_t launch_rec_t(int M, const double* Qi, const double* Qd, const 
   const uint64_t count = host_binom(M, D);
   if (count == 0) return hipSuccess;
   const int block = 256;
-  const uint64_t grid = std::min<uint64_t>((count + block - 1) / block, kMaxGrid);
+  const uint64_t grid = std::min<uint64_t>((count + block - 1) / block, kRecGrid);
   const size_t lds = (size_t)(D + 1) * (M + 1) * sizeof(Idx);
   if (lds <= 48 * 1024) {
     hipLaunchKernelGGL((forward_rec_kernel<D, CONV, WC, true, Idx, MX>), dim3((unsigned)grid),
@@ -356,6 +425,8 @@ hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const d
                          m_out, k_out, p_out, st);
     return hipGetLastError();
   }
+  if (tile_supported(d, M, flags))
+    return launch_forward_tile(d, M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
   switch (d) {
     case 2: return launch_rec_c<2>(M, flags, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
     case 3: return launch_rec_c<3>(M, flags, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);

@@ -1,0 +1,411 @@
+// Tiled order-recursive forward kernel (FP64, orders 3..5): the work that
+// depends only on B = S \ {a} is done once per B and shared, through LDS, by
+// the lanes that handle the subsets {a} + B, a < min B.
+//
+// Colex ranks are B-major: the subsets {a} + B, a = 0 .. b_0 - 1, occupy the
+// consecutive ranks base(B) + a with base(B) = sum_j C(b_j, j + 2), and the
+// B-blocks follow the colex order of the (d-1)-subsets B.  A tile is kTileB
+// consecutive B's (colex index beta, rank sum_j C(b_j, j + 1)) and so a
+// contiguous range of output ranks.
+//
+// Phase 1 (one lane per B, wave 0): unrank B, factor Q_B = L L^T (Cholesky in
+// the interleaved mode order b_0, b_1, .., e), and store in LDS what every
+// subset {a} + B needs besides a:
+//   L (strictly lower part and 1/L_ii), p(B') and p(B)  (B' = B \ {e}),
+//   m(B), m(W) for the non-empty W subset of B', k(R + {e}) for R subset of B'
+//   (read from the tables of the lower orders), and the rank parts of the
+//   per-subset table reads.
+// Phase 2 (all lanes, consecutive ranks across a wavefront): for S = {a} + B
+//   1. y = L^{-1} Q_{B,a} by forward substitution; the Schur complement of
+//      Q_B in Q_S is Q_aa - y^T y, and its partial sums after the rows of B'
+//      give the Schur complement of Q_B' in Q_{S \ e}.  With
+//      det(Q_{U + a}) = det(Q_U) det(Q_aa - y_U^T y_U) (App. D.1, Eq.
+//      vacuum_gaussian_prob: p(T) = det(Q_T)^(-1/2)) this yields p(S \ e) and
+//      p(S) from two 2x2 determinants;
+//   2. the other p({a} + U), U subset of B, come from the lower-order tables;
+//   3. m(S \ e) = m(B') - nu(B') and m(S) = m(B) - nu(B), nu(W) the signed sum
+//      of p({a} + U) over U subset of W (the inclusion-exclusion of Eq.
+//      corre_cov_main split by whether T contains a; parity analogous);
+//   4. k(S) = m(S) - sum_{T proper, e in T} k(T) m(S \ T)  (the partition sum of
+//      Eq. cumulant_corr_main grouped by the block containing e), with the
+//      k(T), m(S \ T) of lower order read from LDS (when they do not contain a)
+//      or from the tables (when they do).
+// Per subset that is one forward substitution of a 2(d-1) x 2 block, two 2x2
+// determinants and 2^d + 2^(d-1) additions; the factorisation of Q_B is paid
+// once per B (about 29 subsets on average at M = 144, d = 5).
+#include <hip/hip_runtime.h>
+
+#include "gbs_internal.h"
+
+namespace gbs {
+
+namespace {
+
+constexpr int kTileB = 64;        // B's per tile (one per lane of wave 0)
+constexpr int kTileThreads = 256;  // threads per workgroup
+
+// Per-B record in LDS.  Doubles first (16-byte aligned), then 32-bit words.
+template <int NB>
+struct TileLayout {
+  static constexpr int N = 2 * NB;                 // rows of Q_B
+  static constexpr int NU = 1 << NB;               // subsets of B
+  static constexpr int NP = 1 << (NB - 1);         // subsets of B'
+  static constexpr int FULL = NU - 1;
+  static constexpr int FULLP = NP - 1;
+  // doubles
+  static constexpr int dL = 0;                     // tri(i, j): L_ij (j < i), tri(i, i): 1/L_ii
+  static constexpr int dP = tri_size(N);           // p(B'), p(B)
+  static constexpr int dMB = dP + 2;               // m(B)
+  static constexpr int dMW = dMB + 1;              // m(W), W = 1 .. FULLP (index W - 1)
+  static constexpr int dKB = dMW + (NP - 1);       // k(R + e), R = 0 .. FULLP
+  static constexpr int nD = dKB + NP;
+  static constexpr int nDpad = (nD + 1) & ~1;
+  // 32-bit words
+  static constexpr int wStart = 0;                 // first rank of the B-block, tile relative
+  static constexpr int wRow = 1;                   // byte offset of row 2 b_j of Q (NB words)
+  static constexpr int wOP = wRow + NB;            // rank parts of p({a} + U), U != B, B'
+  static constexpr int nOP = NU - 2;
+  static constexpr int wOM = wOP + nOP;            // rank parts of m({a} + W), 0 < W < B'
+  static constexpr int nOM = NP - 2 > 0 ? NP - 2 : 0;
+  static constexpr int wOK = wOM + nOM;            // rank parts of k({a} + R + e), R < B'
+  static constexpr int nOK = NP - 1;
+  static constexpr int nW = wOK + nOK;
+  static constexpr int nWpad = (nW + 3) & ~3;
+  static constexpr int bytes = nDpad * 8 + nWpad * 4;  // multiple of 16
+};
+
+// Index of U among the loaded p({a} + U): U = 0 .. FULL without FULLP and FULL.
+template <int NB>
+__host__ __device__ constexpr int op_index(int u) {
+  return u < (1 << (NB - 1)) - 1 ? u : u - 1;  // skips FULLP; FULL is last and unused
+}
+
+}  // namespace
+
+template <int D, int CONV, bool WANT_CUM>
+__global__ __launch_bounds__(kTileThreads) void forward_tile_kernel(
+    const double* __restrict__ Qi, const double* __restrict__ Qd, int M, uint64_t nB,
+    const uint64_t* __restrict__ binom, OrderTables tab, double* __restrict__ m_out,
+    double* __restrict__ k_out, double* __restrict__ p_out, DeviceStatus* __restrict__ st,
+    int nwin_max) {
+  constexpr int NB = D - 1;
+  using TL = TileLayout<NB>;
+  constexpr int N = TL::N;
+  constexpr int NP = TL::NP;
+  constexpr int FULL = TL::FULL;
+  constexpr int FULLP = TL::FULLP;
+  constexpr int EBIT = 1 << (NB - 1);
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  // [records kTileB x TL::bytes][binomials (D+1) x (M+1) u32][bitmap nwin u64][first slot nwin u8]
+  unsigned char* rec = smem;
+  uint32_t* bin = reinterpret_cast<uint32_t*>(smem + kTileB * TL::bytes);
+  const int ld = M + 1;
+  uint64_t* bits = reinterpret_cast<uint64_t*>(bin + (((D + 1) * ld + 1) & ~1));
+  unsigned char* first = reinterpret_cast<unsigned char*>(bits + nwin_max);
+  __shared__ uint32_t s_ntile;  // ranks in the tile
+  __shared__ uint32_t s_r0lo, s_r0hi;
+
+  for (int i = threadIdx.x; i < (D + 1) * ld; i += blockDim.x) {
+    const int kk = i / ld, nn = i - kk * ld;
+    bin[i] = (uint32_t)binom[kk * kBinLd + nn];
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const uint64_t ntiles = (nB + kTileB - 1) / kTileB;
+  const size_t ldq8 = 2 * (size_t)M * sizeof(double);
+
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();  // previous tile's readers are done; binomials are visible
+    for (int i = threadIdx.x; i < nwin_max; i += blockDim.x) bits[i] = 0;
+    __syncthreads();
+
+    if (wave == 0) {
+      // ---------------- phase 1: one lane per B ----------------
+      const uint64_t beta = tile * kTileB + lane;
+      const bool valid = beta < nB;
+      int b[NB];
+      colex_unrank_est<NB>(valid ? beta : 0, M, bin, ld, b);
+      uint64_t base = 0;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) base += bin[(j + 2) * ld + b[j]];
+      const uint32_t r0lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+      const uint32_t r0hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+      const uint64_t r0 = ((uint64_t)r0hi << 32) | r0lo;
+      const bool nonempty = valid && b[0] >= 1;
+      const uint64_t mask = __ballot(nonempty);
+      const int c = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+      // ranks in the tile: end of the last non-empty block
+      const uint32_t start = (uint32_t)(base - r0);
+      const uint32_t end = nonempty ? start + (uint32_t)b[0] : 0u;
+      uint32_t ntile = end;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) ntile = max(ntile, (uint32_t)__shfl_xor((int)ntile, off));
+      if (lane == 0) {
+        s_ntile = ntile;
+        s_r0lo = r0lo;
+        s_r0hi = r0hi;
+      }
+      if (nonempty) {
+        double* rd = reinterpret_cast<double*>(rec + c * TL::bytes);
+        uint32_t* rw = reinterpret_cast<uint32_t*>(rec + c * TL::bytes + TL::nDpad * 8);
+        // Cholesky of Q_B (modes b_0 .. b_{NB-1}, interleaved x, p)
+        Tri<N> A;
+        gather_q<NB>(Qi, M, b, A);
+        bool bad = false;
+        double dinv[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+#pragma unroll
+          for (int j = 0; j < i; ++j) {
+            double v = A.a[tri(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) v = fma(-A.a[tri(i, k)], A.a[tri(j, k)], v);
+            A.a[tri(i, j)] = v * dinv[j];
+          }
+          double dd = A.a[tri(i, i)];
+#pragma unroll
+          for (int k = 0; k < i; ++k) dd = fma(-A.a[tri(i, k)], A.a[tri(i, k)], dd);
+          bad |= !(dd > 0.0) || !(dd < INFINITY);
+          dinv[i] = rsqrt_f64(dd);
+          A.a[tri(i, i)] = dinv[i];
+        }
+        if (bad) latch_failure(st, D, (int64_t)(r0 + start));
+        double pBp = 1.0;
+#pragma unroll
+        for (int i = 0; i < N - 2; ++i) pBp *= dinv[i];
+        const double pB = pBp * dinv[N - 2] * dinv[N - 1];
+#pragma unroll
+        for (int i = 0; i < tri_size(N); ++i) rd[TL::dL + i] = A.a[i];
+        rd[TL::dP] = pBp;
+        rd[TL::dP + 1] = pB;
+        // binomials C(b_j, k) for the rank arithmetic
+        uint32_t cb[NB][NB + 2];
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+          for (int kk = 1; kk <= NB + 1; ++kk) cb[j][kk] = bin[kk * ld + b[j]];
+        rd[TL::dMB] = load_at(tab.m[NB], (uint32_t)beta);
+#pragma unroll
+        for (int w = 1; w < NP; ++w) {  // m(W), W non-empty subset of B'
+          uint32_t rk = 0;
+          int pos = 0;
+#pragma unroll
+          for (int j = 0; j < NB - 1; ++j)
+            if (w & (1 << j)) rk += cb[j][(pos++) + 1];
+          rd[TL::dMW + w - 1] = load_at(tab.m[popcount_c((unsigned)w)], rk);
+        }
+        if constexpr (WANT_CUM) {
+#pragma unroll
+          for (int R = 0; R < NP; ++R) {  // k(R + e)
+            uint32_t rk = 0;
+            int pos = 0;
+#pragma unroll
+            for (int j = 0; j < NB - 1; ++j)
+              if (R & (1 << j)) rk += cb[j][(pos++) + 1];
+            rk += cb[NB - 1][pos + 1];
+            rd[TL::dKB + R] = load_at(tab.k[pos + 1], rk);
+          }
+        }
+        rw[TL::wStart] = start;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) rw[TL::wRow + j] = (uint32_t)(2 * (size_t)b[j] * ldq8);
+        // rank parts (a at position 0, so element at position pos of U adds C(u, pos + 2))
+#pragma unroll
+        for (int u = 0; u < FULL; ++u) {
+          if (u == FULLP) continue;
+          uint32_t rk = 0;
+          int pos = 0;
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            if (u & (1 << j)) rk += cb[j][(pos++) + 2];
+          rw[TL::wOP + op_index<NB>(u)] = rk;
+        }
+#pragma unroll
+        for (int w = 1; w < FULLP; ++w) {
+          uint32_t rk = 0;
+          int pos = 0;
+#pragma unroll
+          for (int j = 0; j < NB - 1; ++j)
+            if (w & (1 << j)) rk += cb[j][(pos++) + 2];
+          rw[TL::wOM + w - 1] = rk;
+        }
+        if constexpr (WANT_CUM) {
+#pragma unroll
+          for (int R = 0; R < FULLP; ++R) {
+            uint32_t rk = 0;
+            int pos = 0;
+#pragma unroll
+            for (int j = 0; j < NB - 1; ++j)
+              if (R & (1 << j)) rk += cb[j][(pos++) + 2];
+            rk += cb[NB - 1][pos + 2];
+            rw[TL::wOK + R] = rk;
+          }
+        }
+        // run start bit, and first slot of every 64-rank window the run covers
+        atomicOr(reinterpret_cast<unsigned int*>(bits) + (start >> 5), 1u << (start & 31));
+        for (uint32_t w = (start + 63) >> 6; (w << 6) < end; ++w) first[w] = (unsigned char)c;
+      }
+    }
+    __syncthreads();
+
+    // ---------------- phase 2: one lane per subset ----------------
+    const uint32_t ntile = s_ntile;
+    const uint64_t r0 = ((uint64_t)s_r0hi << 32) | s_r0lo;
+    const uint64_t lane_mask = lane == 63 ? ~1ull : ((2ull << lane) - 2ull);  // bits 1 .. lane
+    for (uint32_t w = wave; (w << 6) < ntile; w += kTileThreads / 64) {
+      const uint32_t p = (w << 6) + lane;
+      if (p >= ntile) continue;
+      const int c = (int)first[w] + __popcll(bits[w] & lane_mask);
+      const double* rd = reinterpret_cast<const double*>(rec + c * TL::bytes);
+      const uint32_t* rw = reinterpret_cast<const uint32_t*>(rec + c * TL::bytes + TL::nDpad * 8);
+      const uint32_t a = p - rw[TL::wStart];
+      const uint32_t r = (uint32_t)(r0 + p);
+
+      // table reads (issued first; the factorisation below hides their latency)
+      double pu[1 << NB];
+#pragma unroll
+      for (int u = 0; u < FULL; ++u) {
+        if (u == FULLP) continue;
+        pu[u] = load_at(tab.p[popcount_c((unsigned)u) + 1], rw[TL::wOP + op_index<NB>(u)] + a);
+      }
+      double mwa[NP];  // m({a} + W), W subset of B' (W = 0 and B' filled below)
+      double kra[NP];  // k({a} + R + e), R proper subset of B'
+      if constexpr (WANT_CUM) {
+#pragma unroll
+        for (int w = 1; w < FULLP; ++w)
+          mwa[w] = load_at(tab.m[popcount_c((unsigned)w) + 1], rw[TL::wOM + w - 1] + a);
+#pragma unroll
+        for (int R = 0; R < FULLP; ++R)
+          kra[R] = load_at(tab.k[popcount_c((unsigned)R) + 2], rw[TL::wOK + R] + a);
+      }
+
+      // y = L^{-1} Q_{B,a}; Schur complement s = Q_aa - y^T y
+      const double2 qd0 = *reinterpret_cast<const double2*>(Qd + 4 * (size_t)a);
+      const double qd2 = Qd[4 * (size_t)a + 2];
+      double s00 = qd0.x, s10 = qd0.y, s11 = qd2;
+      double y0[N], y1[N];
+      const char* qcol = reinterpret_cast<const char*>(Qi) + 16 * (size_t)a;
+      double pA = 1.0, pS = 1.0;
+      bool bad = false;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int j = i >> 1;
+        const double2 q = *reinterpret_cast<const double2*>(qcol + rw[TL::wRow + j] + (i & 1) * ldq8);
+        double v0 = q.x, v1 = q.y;
+#pragma unroll
+        for (int k = 0; k < i; ++k) {
+          const double l = rd[TL::dL + tri(i, k)];
+          v0 = fma(-l, y0[k], v0);
+          v1 = fma(-l, y1[k], v1);
+        }
+        const double di = rd[TL::dL + tri(i, i)];
+        y0[i] = v0 * di;
+        y1[i] = v1 * di;
+        s00 = fma(-y0[i], y0[i], s00);
+        s10 = fma(-y0[i], y1[i], s10);
+        s11 = fma(-y1[i], y1[i], s11);
+        if (i == N - 3 || i == N - 1) {
+          const double det = fma(s00, s11, -s10 * s10);
+          bad |= !(s00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
+          const double yv = rsqrt_f64(det);
+          if (i == N - 3) pA = rd[TL::dP] * yv;
+          else pS = rd[TL::dP + 1] * yv;
+        }
+      }
+      if (bad) latch_failure(st, D, (int64_t)(r0 + p));
+      pu[FULLP] = pA;
+      pu[FULL] = pS;
+
+      // correlators of S \ e and S
+      double nuP = 0.0, nuE = 0.0;  // nu(B') and the e-containing part of nu(B)
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        const int t = popcount_c((unsigned)u);
+        const double sw = (CONV == GBS_CLICK) ? ((t & 1) ? -1.0 : 1.0)
+                                              : ((t & 1) ? -1.0 : 1.0) * (double)(1 << t);
+        nuP = fma(sw, pu[u], nuP);
+        nuE = fma(CONV == GBS_CLICK ? -sw : -2.0 * sw, pu[u | EBIT], nuE);
+      }
+      const double nuB = nuP + nuE;
+      const double mBp = rd[TL::dMW + FULLP - 1];
+      const double mB = rd[TL::dMB];
+      double mSe, mS;
+      if constexpr (CONV == GBS_CLICK) {
+        mSe = mBp - nuP;
+        mS = mB - nuB;
+      } else {
+        mSe = fma(((NB - 1) & 1) ? -2.0 : 2.0, nuP, -mBp);
+        mS = fma((NB & 1) ? -2.0 : 2.0, nuB, -mB);
+      }
+      if (m_out) store_at(m_out, r, mS);
+      if (p_out) store_at(p_out, r, pS);
+
+      if constexpr (WANT_CUM) {
+        mwa[0] = (CONV == GBS_CLICK) ? 1.0 - pu[0] : fma(2.0, pu[0], -1.0);  // m({a})
+        mwa[FULLP] = mSe;
+        // k(S) = m(S) - sum over R subset of B' of k(R + e) m({a} + B' \ R)
+        //             - sum over R proper subset of B' of k({a} + R + e) m(B' \ R)
+        double v = mS;
+#pragma unroll
+        for (int R = 0; R < NP; ++R) v = fma(-rd[TL::dKB + R], mwa[FULLP ^ R], v);
+#pragma unroll
+        for (int R = 0; R < FULLP; ++R) v = fma(-kra[R], rd[TL::dMW + (FULLP ^ R) - 1], v);
+        store_at(k_out, r, v);
+      }
+    }
+  }
+}
+
+bool tile_supported(int d, int M, int flags) {
+  if (d < 3 || d > kMaxOrder || (flags & GBS_MIXED)) return false;
+  for (int q = 1; q <= d; ++q)
+    if (host_binom(M, q) >= (1ull << 29)) return false;
+  return true;
+}
+
+template <int D, int CONV, bool WC>
+static hipError_t launch_tile_t(int M, const double* Qi, const double* Qd, const uint64_t* binom,
+                                const OrderTables& tab, double* m_out, double* k_out,
+                                double* p_out, DeviceStatus* st, hipStream_t s) {
+  constexpr int NB = D - 1;
+  const uint64_t nB = host_binom(M, NB);
+  const uint64_t ntiles = (nB + kTileB - 1) / kTileB;
+  if (ntiles == 0 || host_binom(M, D) == 0) return hipSuccess;
+  // ranks per tile <= kTileB * (M - NB): the run of B has b_0 <= M - NB subsets
+  const int nwin = (int)((kTileB * (uint64_t)(M - NB) + 63) / 64) + 1;
+  const size_t lds = (size_t)kTileB * TileLayout<NB>::bytes +
+                     (size_t)(((D + 1) * (M + 1) + 1) & ~1) * sizeof(uint32_t) +
+                     (size_t)nwin * (sizeof(uint64_t) + 1);
+  if (lds > 64 * 1024) return hipErrorInvalidConfiguration;
+  const uint64_t grid = std::min<uint64_t>(ntiles, kMaxGrid);
+  hipLaunchKernelGGL((forward_tile_kernel<D, CONV, WC>), dim3((unsigned)grid), dim3(kTileThreads),
+                     lds, s, Qi, Qd, M, nB, binom, tab, m_out, k_out, p_out, st, nwin);
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_tile_c(int M, int flags, const double* Qi, const double* Qd,
+                                const uint64_t* binom, const OrderTables& tab, double* m_out,
+                                double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
+  if (flags & GBS_PARITY) {
+    if (k_out) return launch_tile_t<D, GBS_PARITY, true>(M, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
+    return launch_tile_t<D, GBS_PARITY, false>(M, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
+  }
+  if (k_out) return launch_tile_t<D, GBS_CLICK, true>(M, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
+  return launch_tile_t<D, GBS_CLICK, false>(M, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
+}
+
+hipError_t launch_forward_tile(int d, int M, int flags, const double* Qi, const double* Qd,
+                               const uint64_t* binom, const OrderTables& tab, double* m_out,
+                               double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
+  switch (d) {
+    case 3: return launch_tile_c<3>(M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
+    case 4: return launch_tile_c<4>(M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
+    case 5: return launch_tile_c<5>(M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace gbs

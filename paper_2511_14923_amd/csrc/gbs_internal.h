@@ -57,6 +57,21 @@ hipError_t launch_forward(int d, int M, int flags, const double* Qi, const doubl
                           const float* E, const uint64_t* binom, double* corr, double* cum,
                           double* ptab, DeviceStatus* st, hipStream_t s);
 
+// Lower-order tables read by the order-recursive kernels: p[q], m[q], k[q]
+// point at the order-q blocks (q below the order being computed).
+struct OrderTables {
+  const double* p[kMaxOrder + 1];  // vacuum probabilities
+  const double* m[kMaxOrder + 1];  // correlators
+  const double* k[kMaxOrder + 1];  // cumulants
+};
+
+// Tiled FP64 kernel of order d (3..5) when every table of orders <= d has
+// fewer than 2^29 entries (32-bit rank arithmetic); see gbs_forward_tile.hip.
+bool tile_supported(int d, int M, int flags);
+hipError_t launch_forward_tile(int d, int M, int flags, const double* Qi, const double* Qd,
+                               const uint64_t* binom, const OrderTables& tab, double* m_out,
+                               double* k_out, double* p_out, DeviceStatus* st, hipStream_t s);
+
 // Order-recursive FP64 forward pass of order d (see gbs_forward_rec.hip):
 // p_tab/m_tab/k_tab[q] point at the order-q blocks of the lower-order tables
 // (q < d); m_out, k_out, p_out at the order-d blocks (each may be null).
