@@ -267,6 +267,10 @@ __device__ __forceinline__ double load_at(const double* __restrict__ base, uint3
 __device__ __forceinline__ double load_at(const double* __restrict__ base, uint64_t idx) {
   return base[idx];
 }
+// Two doubles at a 32-bit byte offset (16-byte aligned) from a uniform base.
+__device__ __forceinline__ double2 load2_at(const double* __restrict__ base, uint32_t byte_off) {
+  return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + byte_off);
+}
 __device__ __forceinline__ void store_at(double* __restrict__ base, uint32_t idx, double v) {
   *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (idx << 3)) = v;
 }

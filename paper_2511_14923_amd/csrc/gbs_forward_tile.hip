@@ -42,7 +42,7 @@ namespace gbs {
 namespace {
 
 constexpr int kTileB = 64;        // B's per tile (one per lane of wave 0)
-constexpr int kTileThreads = 256;  // threads per workgroup
+constexpr int kTileThreads = 256;  // threads per workgroup (4 waves)
 
 // Per-B record in LDS.  Doubles first (16-byte aligned), then 32-bit words.
 template <int NB>
@@ -54,8 +54,8 @@ struct TileLayout {
   static constexpr int FULLP = NP - 1;
   // doubles
   static constexpr int dL = 0;                     // tri(i, j): L_ij (j < i), tri(i, i): 1/L_ii
-  static constexpr int dP = tri_size(N);           // p(B'), p(B)
-  static constexpr int dMB = dP + 2;               // m(B)
+  static constexpr int dP = tri_size(N);           // p(b_0 .. b_j), j = 0 .. NB-1
+  static constexpr int dMB = dP + NB;              // m(B)
   static constexpr int dMW = dMB + 1;              // m(W), W = 1 .. FULLP (index W - 1)
   static constexpr int dKB = dMW + (NP - 1);       // k(R + e), R = 0 .. FULLP
   static constexpr int nD = dKB + NP;
@@ -63,21 +63,25 @@ struct TileLayout {
   // 32-bit words
   static constexpr int wStart = 0;                 // first rank of the B-block, tile relative
   static constexpr int wRow = 1;                   // byte offset of row 2 b_j of Q (NB words)
-  static constexpr int wOP = wRow + NB;            // rank parts of p({a} + U), U != B, B'
-  static constexpr int nOP = NU - 2;
-  static constexpr int wOM = wOP + nOP;            // rank parts of m({a} + W), 0 < W < B'
-  static constexpr int nOM = NP - 2 > 0 ? NP - 2 : 0;
-  static constexpr int wOK = wOM + nOM;            // rank parts of k({a} + R + e), R < B'
+  static constexpr int wOP = wRow + NB;            // rank parts of p({a} + U), U not a prefix
+  static constexpr int nOP = NU - (NB + 1);
+  static constexpr int wOK = wOP + nOP;            // rank parts of k({a} + R + e), R < B'
   static constexpr int nOK = NP - 1;
   static constexpr int nW = wOK + nOK;
   static constexpr int nWpad = (nW + 3) & ~3;
   static constexpr int bytes = nDpad * 8 + nWpad * 4;  // multiple of 16
 };
 
-// Index of U among the loaded p({a} + U): U = 0 .. FULL without FULLP and FULL.
-template <int NB>
+// U = {b_0 .. b_j} (bit mask 2^(j+1) - 1, or 0) is a prefix of B in the
+// elimination order: p({a} + U) comes from the factorisation, the other
+// p({a} + U) are read from the tables.
+__host__ __device__ constexpr bool is_prefix(int u) { return (u & (u + 1)) == 0; }
+
+// Index of a non-prefix U among the table reads.
 __host__ __device__ constexpr int op_index(int u) {
-  return u < (1 << (NB - 1)) - 1 ? u : u - 1;  // skips FULLP; FULL is last and unused
+  int n = 0;
+  for (int v = 0; v < u; ++v) n += is_prefix(v) ? 0 : 1;
+  return n;
 }
 
 }  // namespace
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(kTileThreads) void forward_tile_kernel(
   uint64_t* bits = reinterpret_cast<uint64_t*>(bin + (((D + 1) * ld + 1) & ~1));
   unsigned char* first = reinterpret_cast<unsigned char*>(bits + nwin_max);
   __shared__ uint32_t s_ntile;  // ranks in the tile
-  __shared__ uint32_t s_r0lo, s_r0hi;
+  __shared__ uint32_t s_r0;     // rank of the tile's first subset
 
   for (int i = threadIdx.x; i < (D + 1) * ld; i += blockDim.x) {
     const int kk = i / ld, nn = i - kk * ld;
@@ -113,146 +117,154 @@ __global__ __launch_bounds__(kTileThreads) void forward_tile_kernel(
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const uint64_t ntiles = (nB + kTileB - 1) / kTileB;
-  const size_t ldq8 = 2 * (size_t)M * sizeof(double);
+  const uint32_t ldq8 = 2u * (uint32_t)M * (uint32_t)sizeof(double);
+  const double* Qodd = Qi + 2 * (size_t)M;  // odd rows (p quadratures)
 
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     __syncthreads();  // previous tile's readers are done; binomials are visible
     for (int i = threadIdx.x; i < nwin_max; i += blockDim.x) bits[i] = 0;
     __syncthreads();
 
-    if (wave == 0) {
-      // ---------------- phase 1: one lane per B ----------------
+    // ---------------- phase 1: lane = B, wave = part of the record ----------------
+    {
       const uint64_t beta = tile * kTileB + lane;
       const bool valid = beta < nB;
       int b[NB];
       colex_unrank_est<NB>(valid ? beta : 0, M, bin, ld, b);
-      uint64_t base = 0;
+      uint32_t base = 0;
 #pragma unroll
       for (int j = 0; j < NB; ++j) base += bin[(j + 2) * ld + b[j]];
-      const uint32_t r0lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-      const uint32_t r0hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-      const uint64_t r0 = ((uint64_t)r0hi << 32) | r0lo;
+      const uint32_t r0 = __builtin_amdgcn_readfirstlane(base);
       const bool nonempty = valid && b[0] >= 1;
       const uint64_t mask = __ballot(nonempty);
       const int c = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-      // ranks in the tile: end of the last non-empty block
-      const uint32_t start = (uint32_t)(base - r0);
+      const uint32_t start = base - r0;  // first rank of this B's run, tile relative
       const uint32_t end = nonempty ? start + (uint32_t)b[0] : 0u;
-      uint32_t ntile = end;
+      double* rd = reinterpret_cast<double*>(rec + c * TL::bytes);
+      uint32_t* rw = reinterpret_cast<uint32_t*>(rec + c * TL::bytes + TL::nDpad * 8);
+      if (wave == 0) {
+        if (nonempty) {
+          // Cholesky of Q_B (modes b_0 .. b_{NB-1}, interleaved x, p)
+          Tri<N> A;
+          gather_q<NB>(Qi, M, b, A);
+          bool bad = false;
+          double dinv[N];
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) ntile = max(ntile, (uint32_t)__shfl_xor((int)ntile, off));
-      if (lane == 0) {
-        s_ntile = ntile;
-        s_r0lo = r0lo;
-        s_r0hi = r0hi;
-      }
-      if (nonempty) {
-        double* rd = reinterpret_cast<double*>(rec + c * TL::bytes);
-        uint32_t* rw = reinterpret_cast<uint32_t*>(rec + c * TL::bytes + TL::nDpad * 8);
-        // Cholesky of Q_B (modes b_0 .. b_{NB-1}, interleaved x, p)
-        Tri<N> A;
-        gather_q<NB>(Qi, M, b, A);
-        bool bad = false;
-        double dinv[N];
+          for (int i = 0; i < N; ++i) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
+            for (int j = 0; j < i; ++j) {
+              double v = A.a[tri(i, j)];
 #pragma unroll
-          for (int j = 0; j < i; ++j) {
-            double v = A.a[tri(i, j)];
+              for (int k = 0; k < j; ++k) v = fma(-A.a[tri(i, k)], A.a[tri(j, k)], v);
+              A.a[tri(i, j)] = v * dinv[j];
+            }
+            double dd = A.a[tri(i, i)];
 #pragma unroll
-            for (int k = 0; k < j; ++k) v = fma(-A.a[tri(i, k)], A.a[tri(j, k)], v);
-            A.a[tri(i, j)] = v * dinv[j];
+            for (int k = 0; k < i; ++k) dd = fma(-A.a[tri(i, k)], A.a[tri(i, k)], dd);
+            bad |= !(dd > 0.0) || !(dd < INFINITY);
+            dinv[i] = rsqrt_f64(dd);
+            A.a[tri(i, i)] = dinv[i];
           }
-          double dd = A.a[tri(i, i)];
+          if (bad) latch_failure(st, D, (int64_t)base);
 #pragma unroll
-          for (int k = 0; k < i; ++k) dd = fma(-A.a[tri(i, k)], A.a[tri(i, k)], dd);
-          bad |= !(dd > 0.0) || !(dd < INFINITY);
-          dinv[i] = rsqrt_f64(dd);
-          A.a[tri(i, i)] = dinv[i];
-        }
-        if (bad) latch_failure(st, D, (int64_t)(r0 + start));
-        double pBp = 1.0;
+          for (int i = 0; i < tri_size(N); ++i) rd[TL::dL + i] = A.a[i];
+          double pj = 1.0;  // p(b_0 .. b_j) = product of 1 / L_ii over its rows
 #pragma unroll
-        for (int i = 0; i < N - 2; ++i) pBp *= dinv[i];
-        const double pB = pBp * dinv[N - 2] * dinv[N - 1];
-#pragma unroll
-        for (int i = 0; i < tri_size(N); ++i) rd[TL::dL + i] = A.a[i];
-        rd[TL::dP] = pBp;
-        rd[TL::dP + 1] = pB;
-        // binomials C(b_j, k) for the rank arithmetic
-        uint32_t cb[NB][NB + 2];
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-#pragma unroll
-          for (int kk = 1; kk <= NB + 1; ++kk) cb[j][kk] = bin[kk * ld + b[j]];
-        rd[TL::dMB] = load_at(tab.m[NB], (uint32_t)beta);
-#pragma unroll
-        for (int w = 1; w < NP; ++w) {  // m(W), W non-empty subset of B'
-          uint32_t rk = 0;
-          int pos = 0;
-#pragma unroll
-          for (int j = 0; j < NB - 1; ++j)
-            if (w & (1 << j)) rk += cb[j][(pos++) + 1];
-          rd[TL::dMW + w - 1] = load_at(tab.m[popcount_c((unsigned)w)], rk);
-        }
-        if constexpr (WANT_CUM) {
-#pragma unroll
-          for (int R = 0; R < NP; ++R) {  // k(R + e)
-            uint32_t rk = 0;
-            int pos = 0;
-#pragma unroll
-            for (int j = 0; j < NB - 1; ++j)
-              if (R & (1 << j)) rk += cb[j][(pos++) + 1];
-            rk += cb[NB - 1][pos + 1];
-            rd[TL::dKB + R] = load_at(tab.k[pos + 1], rk);
+          for (int j = 0; j < NB; ++j) {
+            pj *= dinv[2 * j] * dinv[2 * j + 1];
+            rd[TL::dP + j] = pj;
           }
         }
-        rw[TL::wStart] = start;
-#pragma unroll
-        for (int j = 0; j < NB; ++j) rw[TL::wRow + j] = (uint32_t)(2 * (size_t)b[j] * ldq8);
-        // rank parts (a at position 0, so element at position pos of U adds C(u, pos + 2))
-#pragma unroll
-        for (int u = 0; u < FULL; ++u) {
-          if (u == FULLP) continue;
-          uint32_t rk = 0;
-          int pos = 0;
+      } else if (wave == 1) {
+        if (nonempty) {
+          // B-only correlators and cumulants from the lower-order tables
+          uint32_t cb[NB][NB + 1];
 #pragma unroll
           for (int j = 0; j < NB; ++j)
-            if (u & (1 << j)) rk += cb[j][(pos++) + 2];
-          rw[TL::wOP + op_index<NB>(u)] = rk;
-        }
 #pragma unroll
-        for (int w = 1; w < FULLP; ++w) {
-          uint32_t rk = 0;
-          int pos = 0;
+            for (int kk = 1; kk <= NB; ++kk) cb[j][kk] = bin[kk * ld + b[j]];
+          rd[TL::dMB] = load_at(tab.m[NB], (uint32_t)beta);
 #pragma unroll
-          for (int j = 0; j < NB - 1; ++j)
-            if (w & (1 << j)) rk += cb[j][(pos++) + 2];
-          rw[TL::wOM + w - 1] = rk;
-        }
-        if constexpr (WANT_CUM) {
-#pragma unroll
-          for (int R = 0; R < FULLP; ++R) {
+          for (int w = 1; w < NP; ++w) {  // m(W), W non-empty subset of B'
             uint32_t rk = 0;
             int pos = 0;
 #pragma unroll
             for (int j = 0; j < NB - 1; ++j)
-              if (R & (1 << j)) rk += cb[j][(pos++) + 2];
-            rk += cb[NB - 1][pos + 2];
-            rw[TL::wOK + R] = rk;
+              if (w & (1 << j)) rk += cb[j][(pos++) + 1];
+            rd[TL::dMW + w - 1] = load_at(tab.m[popcount_c((unsigned)w)], rk);
+          }
+          if constexpr (WANT_CUM) {
+#pragma unroll
+            for (int R = 0; R < NP; ++R) {  // k(R + e)
+              uint32_t rk = 0;
+              int pos = 0;
+#pragma unroll
+              for (int j = 0; j < NB - 1; ++j)
+                if (R & (1 << j)) rk += cb[j][(pos++) + 1];
+              rk += cb[NB - 1][pos + 1];
+              rd[TL::dKB + R] = load_at(tab.k[pos + 1], rk);
+            }
           }
         }
-        // run start bit, and first slot of every 64-rank window the run covers
-        atomicOr(reinterpret_cast<unsigned int*>(bits) + (start >> 5), 1u << (start & 31));
-        for (uint32_t w = (start + 63) >> 6; (w << 6) < end; ++w) first[w] = (unsigned char)c;
+      } else if (wave == 2) {
+        if (nonempty) {
+          // rank parts of the per-subset reads, less the run start: with p the
+          // tile-relative rank of {a} + B, rank({a} + U) = part(U) + a = part(U) - start + p
+          // (a comes first, so the i-th element u_i of U adds C(u_i, i + 2))
+          uint32_t cb[NB][NB + 2];
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int kk = 2; kk <= NB + 1; ++kk) cb[j][kk] = bin[kk * ld + b[j]];
+          rw[TL::wStart] = start;
+#pragma unroll
+          for (int j = 0; j < NB; ++j) rw[TL::wRow + j] = 2u * (uint32_t)b[j] * ldq8;
+#pragma unroll
+          for (int u = 0; u < FULL; ++u) {
+            if (is_prefix(u)) continue;
+            uint32_t rk = 0;
+            int pos = 0;
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+              if (u & (1 << j)) rk += cb[j][(pos++) + 2];
+            rw[TL::wOP + op_index(u)] = rk - start;
+          }
+          if constexpr (WANT_CUM) {
+#pragma unroll
+            for (int R = 0; R < FULLP; ++R) {
+              uint32_t rk = 0;
+              int pos = 0;
+#pragma unroll
+              for (int j = 0; j < NB - 1; ++j)
+                if (R & (1 << j)) rk += cb[j][(pos++) + 2];
+              rk += cb[NB - 1][pos + 2];
+              rw[TL::wOK + R] = rk - start;
+            }
+          }
+        }
+      } else {
+        // ranks in the tile (end of the last non-empty run), the run-start
+        // bitmap and the first run of every 64-rank window
+        uint32_t ntile = end;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+          ntile = max(ntile, (uint32_t)__shfl_xor((int)ntile, off));
+        if (lane == 0) {
+          s_ntile = ntile;
+          s_r0 = r0;
+        }
+        if (nonempty) {
+          atomicOr(reinterpret_cast<unsigned int*>(bits) + (start >> 5), 1u << (start & 31));
+          for (uint32_t w = (start + 63) >> 6; (w << 6) < end; ++w) first[w] = (unsigned char)c;
+        }
       }
     }
     __syncthreads();
 
     // ---------------- phase 2: one lane per subset ----------------
     const uint32_t ntile = s_ntile;
-    const uint64_t r0 = ((uint64_t)s_r0hi << 32) | s_r0lo;
+    const uint32_t r0 = s_r0;
     const uint64_t lane_mask = lane == 63 ? ~1ull : ((2ull << lane) - 2ull);  // bits 1 .. lane
     for (uint32_t w = wave; (w << 6) < ntile; w += kTileThreads / 64) {
       const uint32_t p = (w << 6) + lane;
@@ -261,38 +273,40 @@ __global__ __launch_bounds__(kTileThreads) void forward_tile_kernel(
       const double* rd = reinterpret_cast<const double*>(rec + c * TL::bytes);
       const uint32_t* rw = reinterpret_cast<const uint32_t*>(rec + c * TL::bytes + TL::nDpad * 8);
       const uint32_t a = p - rw[TL::wStart];
-      const uint32_t r = (uint32_t)(r0 + p);
+      const uint32_t r = r0 + p;
 
       // table reads (issued first; the factorisation below hides their latency)
       double pu[1 << NB];
 #pragma unroll
       for (int u = 0; u < FULL; ++u) {
-        if (u == FULLP) continue;
-        pu[u] = load_at(tab.p[popcount_c((unsigned)u) + 1], rw[TL::wOP + op_index<NB>(u)] + a);
+        if (is_prefix(u)) continue;
+        pu[u] = load_at(tab.p[popcount_c((unsigned)u) + 1], rw[TL::wOP + op_index(u)] + p);
       }
-      double mwa[NP];  // m({a} + W), W subset of B' (W = 0 and B' filled below)
       double kra[NP];  // k({a} + R + e), R proper subset of B'
       if constexpr (WANT_CUM) {
 #pragma unroll
-        for (int w = 1; w < FULLP; ++w)
-          mwa[w] = load_at(tab.m[popcount_c((unsigned)w) + 1], rw[TL::wOM + w - 1] + a);
-#pragma unroll
         for (int R = 0; R < FULLP; ++R)
-          kra[R] = load_at(tab.k[popcount_c((unsigned)R) + 2], rw[TL::wOK + R] + a);
+          kra[R] = load_at(tab.k[popcount_c((unsigned)R) + 2], rw[TL::wOK + R] + p);
       }
 
-      // y = L^{-1} Q_{B,a}; Schur complement s = Q_aa - y^T y
-      const double2 qd0 = *reinterpret_cast<const double2*>(Qd + 4 * (size_t)a);
-      const double qd2 = Qd[4 * (size_t)a + 2];
+      // y = L^{-1} Q_{B,a}; the Schur complement of Q_U in Q_{U + a} is
+      // Q_aa - y_U^T y_U for every prefix U = {b_0 .. b_j} of B, so
+      // p({a} + U) = p(U) det(Q_aa - y_U^T y_U)^(-1/2) (p({a}) for U empty)
+      const double2 qd0 = load2_at(Qd, a << 5);
+      const double qd2 = load_at(Qd, 4 * a + 2);
       double s00 = qd0.x, s10 = qd0.y, s11 = qd2;
       double y0[N], y1[N];
-      const char* qcol = reinterpret_cast<const char*>(Qi) + 16 * (size_t)a;
-      double pA = 1.0, pS = 1.0;
       bool bad = false;
+      {
+        const double det = fma(s00, s11, -s10 * s10);
+        bad |= !(s00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
+        pu[0] = rsqrt_f64(det);
+      }
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         const int j = i >> 1;
-        const double2 q = *reinterpret_cast<const double2*>(qcol + rw[TL::wRow + j] + (i & 1) * ldq8);
+        // rows 2 b_j (x) and 2 b_j + 1 (p) of Q, columns 2a, 2a + 1
+        const double2 q = load2_at((i & 1) ? Qodd : Qi, rw[TL::wRow + j] + (a << 4));
         double v0 = q.x, v1 = q.y;
 #pragma unroll
         for (int k = 0; k < i; ++k) {
@@ -306,45 +320,54 @@ __global__ __launch_bounds__(kTileThreads) void forward_tile_kernel(
         s00 = fma(-y0[i], y0[i], s00);
         s10 = fma(-y0[i], y1[i], s10);
         s11 = fma(-y1[i], y1[i], s11);
-        if (i == N - 3 || i == N - 1) {
+        if (i & 1) {
           const double det = fma(s00, s11, -s10 * s10);
           bad |= !(s00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
-          const double yv = rsqrt_f64(det);
-          if (i == N - 3) pA = rd[TL::dP] * yv;
-          else pS = rd[TL::dP + 1] * yv;
+          pu[(2 << j) - 1] = rd[TL::dP + j] * rsqrt_f64(det);
         }
       }
-      if (bad) latch_failure(st, D, (int64_t)(r0 + p));
-      pu[FULLP] = pA;
-      pu[FULL] = pS;
+      if (bad) latch_failure(st, D, (int64_t)r);
+      const double pS = pu[FULL];
 
-      // correlators of S \ e and S
-      double nuP = 0.0, nuE = 0.0;  // nu(B') and the e-containing part of nu(B)
+      // nu(W) = sum over U subset of W of s_|U| p({a} + U) for W subset of B'
+      // (subset zeta transform), then the correlators m({a} + W) = m(W) - nu(W)
+      // (click) or -c(W) + 2 (-1)^|W| nu(W) (parity), m(empty) = 1
+      double nu[NP];
 #pragma unroll
       for (int u = 0; u < NP; ++u) {
         const int t = popcount_c((unsigned)u);
-        const double sw = (CONV == GBS_CLICK) ? ((t & 1) ? -1.0 : 1.0)
-                                              : ((t & 1) ? -1.0 : 1.0) * (double)(1 << t);
-        nuP = fma(sw, pu[u], nuP);
-        nuE = fma(CONV == GBS_CLICK ? -sw : -2.0 * sw, pu[u | EBIT], nuE);
+        nu[u] = (CONV == GBS_CLICK) ? ((t & 1) ? -pu[u] : pu[u])
+                                    : ((t & 1) ? -1.0 : 1.0) * (double)(1 << t) * pu[u];
       }
-      const double nuB = nuP + nuE;
-      const double mBp = rd[TL::dMW + FULLP - 1];
+      double nuE = 0.0;  // the part of nu(B) whose sets contain e
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        const int t = popcount_c((unsigned)u) + 1;
+        nuE = fma((CONV == GBS_CLICK) ? ((t & 1) ? -1.0 : 1.0)
+                                      : ((t & 1) ? -1.0 : 1.0) * (double)(1 << t),
+                  pu[u | EBIT], nuE);
+      }
+#pragma unroll
+      for (int bit = 0; bit < NB - 1; ++bit)
+#pragma unroll
+        for (int u = 0; u < NP; ++u)
+          if (u & (1 << bit)) nu[u] += nu[u ^ (1 << bit)];
+      double mwa[NP];  // m({a} + W), W subset of B'
+#pragma unroll
+      for (int w = 0; w < NP; ++w) {
+        const double mw = w ? rd[TL::dMW + w - 1] : 1.0;
+        if constexpr (CONV == GBS_CLICK) mwa[w] = mw - nu[w];
+        else mwa[w] = fma((popcount_c((unsigned)w) & 1) ? -2.0 : 2.0, nu[w], -mw);
+      }
+      const double nuB = nu[FULLP] + nuE;
       const double mB = rd[TL::dMB];
-      double mSe, mS;
-      if constexpr (CONV == GBS_CLICK) {
-        mSe = mBp - nuP;
-        mS = mB - nuB;
-      } else {
-        mSe = fma(((NB - 1) & 1) ? -2.0 : 2.0, nuP, -mBp);
-        mS = fma((NB & 1) ? -2.0 : 2.0, nuB, -mB);
-      }
+      double mS;
+      if constexpr (CONV == GBS_CLICK) mS = mB - nuB;
+      else mS = fma((NB & 1) ? -2.0 : 2.0, nuB, -mB);
       if (m_out) store_at(m_out, r, mS);
       if (p_out) store_at(p_out, r, pS);
 
       if constexpr (WANT_CUM) {
-        mwa[0] = (CONV == GBS_CLICK) ? 1.0 - pu[0] : fma(2.0, pu[0], -1.0);  // m({a})
-        mwa[FULLP] = mSe;
         // k(S) = m(S) - sum over R subset of B' of k(R + e) m({a} + B' \ R)
         //             - sum over R proper subset of B' of k({a} + R + e) m(B' \ R)
         double v = mS;
