@@ -58,16 +58,15 @@ struct TileLayout {
   static constexpr int dMB = dP + NB;              // m(B)
   static constexpr int dMW = dMB + 1;              // m(W), W = 1 .. FULLP (index W - 1)
   static constexpr int dKB = dMW + (NP - 1);       // k(R + e), R = 0 .. FULLP
-  static constexpr int nD = dKB + NP;
+  static constexpr int dME = dKB + NP;             // m(R + e), R = 0 .. FULLP
+  static constexpr int nD = dME + NP;
   static constexpr int nDpad = (nD + 1) & ~1;
   // 32-bit words
   static constexpr int wStart = 0;                 // first rank of the B-block, tile relative
   static constexpr int wRow = 1;                   // byte offset of row 2 b_j of Q (NB words)
   static constexpr int wOP = wRow + NB;            // rank parts of p({a} + U), U not a prefix
   static constexpr int nOP = NU - (NB + 1);
-  static constexpr int wOK = wOP + nOP;            // rank parts of k({a} + R + e), R < B'
-  static constexpr int nOK = NP - 1;
-  static constexpr int nW = wOK + nOK;
+  static constexpr int nW = wOP + nOP;
   static constexpr int nWpad = (nW + 3) & ~3;
   static constexpr int bytes = nDpad * 8 + nWpad * 4;  // multiple of 16
 };
@@ -204,6 +203,7 @@ __global__ __launch_bounds__(kTileThreads) void forward_tile_kernel(
                 if (R & (1 << j)) rk += cb[j][(pos++) + 1];
               rk += cb[NB - 1][pos + 1];
               rd[TL::dKB + R] = load_at(tab.k[pos + 1], rk);
+              rd[TL::dME + R] = load_at(tab.m[pos + 1], rk);
             }
           }
         }
@@ -229,18 +229,6 @@ __global__ __launch_bounds__(kTileThreads) void forward_tile_kernel(
             for (int j = 0; j < NB; ++j)
               if (u & (1 << j)) rk += cb[j][(pos++) + 2];
             rw[TL::wOP + op_index(u)] = rk - start;
-          }
-          if constexpr (WANT_CUM) {
-#pragma unroll
-            for (int R = 0; R < FULLP; ++R) {
-              uint32_t rk = 0;
-              int pos = 0;
-#pragma unroll
-              for (int j = 0; j < NB - 1; ++j)
-                if (R & (1 << j)) rk += cb[j][(pos++) + 2];
-              rk += cb[NB - 1][pos + 2];
-              rw[TL::wOK + R] = rk - start;
-            }
           }
         }
       } else {
@@ -281,12 +269,6 @@ __global__ __launch_bounds__(kTileThreads) void forward_tile_kernel(
       for (int u = 0; u < FULL; ++u) {
         if (is_prefix(u)) continue;
         pu[u] = load_at(tab.p[popcount_c((unsigned)u) + 1], rw[TL::wOP + op_index(u)] + p);
-      }
-      double kra[NP];  // k({a} + R + e), R proper subset of B'
-      if constexpr (WANT_CUM) {
-#pragma unroll
-        for (int R = 0; R < FULLP; ++R)
-          kra[R] = load_at(tab.k[popcount_c((unsigned)R) + 2], rw[TL::wOK + R] + p);
       }
 
       // y = L^{-1} Q_{B,a}; the Schur complement of Q_U in Q_{U + a} is
@@ -339,19 +321,21 @@ __global__ __launch_bounds__(kTileThreads) void forward_tile_kernel(
         nu[u] = (CONV == GBS_CLICK) ? ((t & 1) ? -pu[u] : pu[u])
                                     : ((t & 1) ? -1.0 : 1.0) * (double)(1 << t) * pu[u];
       }
-      double nuE = 0.0;  // the part of nu(B) whose sets contain e
+      double nue[NP];  // the same over the sets U + e
 #pragma unroll
       for (int u = 0; u < NP; ++u) {
         const int t = popcount_c((unsigned)u) + 1;
-        nuE = fma((CONV == GBS_CLICK) ? ((t & 1) ? -1.0 : 1.0)
-                                      : ((t & 1) ? -1.0 : 1.0) * (double)(1 << t),
-                  pu[u | EBIT], nuE);
+        nue[u] = ((CONV == GBS_CLICK) ? ((t & 1) ? -1.0 : 1.0)
+                                      : ((t & 1) ? -1.0 : 1.0) * (double)(1 << t)) * pu[u | EBIT];
       }
 #pragma unroll
       for (int bit = 0; bit < NB - 1; ++bit)
 #pragma unroll
         for (int u = 0; u < NP; ++u)
-          if (u & (1 << bit)) nu[u] += nu[u ^ (1 << bit)];
+          if (u & (1 << bit)) {
+            nu[u] += nu[u ^ (1 << bit)];
+            nue[u] += nue[u ^ (1 << bit)];
+          }
       double mwa[NP];  // m({a} + W), W subset of B'
 #pragma unroll
       for (int w = 0; w < NP; ++w) {
@@ -359,7 +343,7 @@ __global__ __launch_bounds__(kTileThreads) void forward_tile_kernel(
         if constexpr (CONV == GBS_CLICK) mwa[w] = mw - nu[w];
         else mwa[w] = fma((popcount_c((unsigned)w) & 1) ? -2.0 : 2.0, nu[w], -mw);
       }
-      const double nuB = nu[FULLP] + nuE;
+      const double nuB = nu[FULLP] + nue[FULLP];
       const double mB = rd[TL::dMB];
       double mS;
       if constexpr (CONV == GBS_CLICK) mS = mB - nuB;
@@ -368,14 +352,28 @@ __global__ __launch_bounds__(kTileThreads) void forward_tile_kernel(
       if (p_out) store_at(p_out, r, pS);
 
       if constexpr (WANT_CUM) {
-        // k(S) = m(S) - sum over R subset of B' of k(R + e) m({a} + B' \ R)
-        //             - sum over R proper subset of B' of k({a} + R + e) m(B' \ R)
-        double v = mS;
+        // K(Y) = k(Y + e) for Y subset of X = {a} + B' (bit 0 of Y = a, bit
+        // i + 1 = b_i): B-only ones from LDS, the ones containing a by the
+        // fixed-element recursion K(Y) = m(Y + e) - sum_{R proper subset of Y} K(R) m(Y \ R)
+        constexpr int NX = 2 * NP;
+        double Kv[NX];
 #pragma unroll
-        for (int R = 0; R < NP; ++R) v = fma(-rd[TL::dKB + R], mwa[FULLP ^ R], v);
+        for (int R = 0; R < NP; ++R) Kv[2 * R] = rd[TL::dKB + R];
+        auto mu_x = [&](int Y) -> double {  // m(Y), Y non-empty subset of X
+          return (Y & 1) ? mwa[Y >> 1] : rd[TL::dMW + (Y >> 1) - 1];
+        };
 #pragma unroll
-        for (int R = 0; R < FULLP; ++R) v = fma(-kra[R], rd[TL::dMW + (FULLP ^ R) - 1], v);
-        store_at(k_out, r, v);
+        for (int Y = 1; Y < NX; Y += 2) {
+          const int W = Y >> 1;  // Y = {a} + W
+          double v;
+          if constexpr (CONV == GBS_CLICK) v = rd[TL::dME + W] - (nu[W] + nue[W]);
+          else v = fma((popcount_c((unsigned)W) & 1) ? 2.0 : -2.0, nu[W] + nue[W], -rd[TL::dME + W]);
+#pragma unroll
+          for (int R = 0; R < Y; ++R)
+            if ((R & Y) == R) v = fma(-Kv[R], mu_x(Y ^ R), v);
+          Kv[Y] = v;
+        }
+        store_at(k_out, r, Kv[NX - 1]);
       }
     }
   }
