@@ -33,11 +33,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_forward_order5_m144.json"
 
 
 def kernel_source_hash() -> str:
+    """Hash of the HIP sources with comments and whitespace removed, so that the
+    stored counter readings stay valid across comment-only edits."""
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_14923_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        text = " ".join(text.split())
+        h.update(name.encode() + text.encode())
     return h.hexdigest()[:16]
 
 

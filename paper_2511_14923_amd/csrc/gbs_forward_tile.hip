@@ -8,31 +8,33 @@
 // consecutive B's (colex index beta, rank sum_j C(b_j, j + 1)) and so a
 // contiguous range of output ranks.
 //
-// Phase 1 (one lane per B, wave 0): unrank B, factor Q_B = L L^T (Cholesky in
-// the interleaved mode order b_0, b_1, .., e), and store in LDS what every
-// subset {a} + B needs besides a:
-//   L (strictly lower part and 1/L_ii), p(B') and p(B)  (B' = B \ {e}),
-//   m(B), m(W) for the non-empty W subset of B', k(R + {e}) for R subset of B'
-//   (read from the tables of the lower orders), and the rank parts of the
-//   per-subset table reads.
-// Phase 2 (all lanes, consecutive ranks across a wavefront): for S = {a} + B
-//   1. y = L^{-1} Q_{B,a} by forward substitution; the Schur complement of
-//      Q_B in Q_S is Q_aa - y^T y, and its partial sums after the rows of B'
-//      give the Schur complement of Q_B' in Q_{S \ e}.  With
-//      det(Q_{U + a}) = det(Q_U) det(Q_aa - y_U^T y_U) (App. D.1, Eq.
-//      vacuum_gaussian_prob: p(T) = det(Q_T)^(-1/2)) this yields p(S \ e) and
-//      p(S) from two 2x2 determinants;
+// Phase 1 (lane = B; each wave fills one part of the per-B record in LDS):
+//   wave 0: Q_B = L L^T (Cholesky in the interleaved mode order b_0, .., e),
+//           L with 1/L_ii on its diagonal, and p(b_0 .. b_j) for every prefix;
+//   wave 1: m(B), m(W) for the non-empty W subset of B' = B \ {e}, k(R + {e})
+//           and m(R + {e}) for R subset of B' (lower-order tables);
+//   wave 2: the rank parts of the per-subset table reads;
+//   wave 3: the run-start bitmap and the first run of every 64-rank window.
+// Phase 2 (lane = subset, consecutive ranks across a wavefront), S = {a} + B:
+//   1. y = L^{-1} Q_{B,a} by forward substitution.  For every prefix
+//      U = {b_0 .. b_j} of B, Q_aa - y_U^T y_U is the Schur complement of Q_U
+//      in Q_{U + a}, so p({a} + U) = p(U) det(Q_aa - y_U^T y_U)^(-1/2)
+//      (App. D.1, Eq. vacuum_gaussian_prob: p(T) = det(Q_T)^(-1/2)); with
+//      U = empty this is p({a}), with U = B it is p(S);
 //   2. the other p({a} + U), U subset of B, come from the lower-order tables;
-//   3. m(S \ e) = m(B') - nu(B') and m(S) = m(B) - nu(B), nu(W) the signed sum
-//      of p({a} + U) over U subset of W (the inclusion-exclusion of Eq.
-//      corre_cov_main split by whether T contains a; parity analogous);
-//   4. k(S) = m(S) - sum_{T proper, e in T} k(T) m(S \ T)  (the partition sum of
-//      Eq. cumulant_corr_main grouped by the block containing e), with the
-//      k(T), m(S \ T) of lower order read from LDS (when they do not contain a)
-//      or from the tables (when they do).
-// Per subset that is one forward substitution of a 2(d-1) x 2 block, two 2x2
-// determinants and 2^d + 2^(d-1) additions; the factorisation of Q_B is paid
-// once per B (about 29 subsets on average at M = 144, d = 5).
+//   3. nu(W) and nu(W + e), the signed sums of p({a} + U) over U subset of W
+//      (resp. W + e), W subset of B', by subset zeta transforms; then
+//      m({a} + W) = m(W) - nu(W) and m({a} + W + e) = m(W + e) - nu(W + e)
+//      (the inclusion-exclusion of Eq. corre_cov_main split by whether T
+//      contains a; parity: -c + 2 (-1)^|.| nu with weights (-2)^|U|);
+//   4. the cumulants k(Y + e) of the subsets Y of {a} + B' that contain a, in
+//      increasing order, by k(Y + e) = m(Y + e) - sum_{R proper subset of Y}
+//      k(R + e) m(Y \ R) (the partition sum of Eq. cumulant_corr_main grouped
+//      by the block containing e; App. B, Eq. correlators_expanded_2); the
+//      B-only k(R + e) come from LDS; Y = {a} + B' gives k(S).
+// Per order-5 subset: 11 table reads, 8 16-byte reads of Q, one 8 x 2 forward
+// substitution and five 2x2 determinants; the Cholesky of Q_B is paid once per
+// B (about 29 subsets on average at M = 144).
 #include <hip/hip_runtime.h>
 
 #include "gbs_internal.h"
