@@ -425,6 +425,8 @@ hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const d
                          m_out, k_out, p_out, st);
     return hipGetLastError();
   }
+  if (group_supported(d, M, flags))
+    return launch_forward_group(d, M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
   if (tile_supported(d, M, flags))
     return launch_forward_tile(d, M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
   switch (d) {
