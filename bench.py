@@ -126,6 +126,65 @@ def fp64_parity_sample(np, O, G, inst, corr, cum, n=3000):
     return worst
 
 
+def batched_and_adjoint(P, torch, G, steps):
+    """The two other launch shapes of the path, measured beside the headline:
+    the 48-instance batched launch (M ~ U{40..144}, K = 4, one persistent
+    kernel) and the adjoint at M = 144, K = 3 (vector-Jacobian product of the
+    cumulants with respect to sigma)."""
+    out = {}
+    batch = G.make_batch()
+    bufs = []
+    n_sub = 0
+    flops = 0.0
+    for inst in batch:
+        s = torch.from_numpy(inst.sigma).to("cuda:0")
+        n = P.gbs_total_outputs(inst.M, 4)
+        bufs.append((inst.M, s, torch.empty(n, dtype=torch.float64, device="cuda:0"),
+                     torch.empty(n, dtype=torch.float64, device="cuda:0")))
+        n_sub += n
+        flops += sum(math.comb(inst.M, d) * FLOPS_PER_SUBSET[d] for d in range(1, 5))
+    P.gbs_cumulants_batched(bufs, 4, 0)  # plan, graph capture
+    torch.cuda.synchronize()
+    walls, kern = [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        P.gbs_cumulants_batched(bufs, 4, 0)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        P.gbs_cumulants_batched(bufs, 4, P.GBS_TIMING)
+        kern.append(sum(ms for st, _, ms in P.gbs_last_timings() if st == "batched"))
+    wall = sorted(walls)[len(walls) // 2]
+    kms = sorted(kern)[len(kern) // 2]
+    out["batched48_k4"] = {
+        "instances": len(batch), "subsets": n_sub, "ms_per_call": 1e3 * wall,
+        "subsets_per_s": n_sub / wall, "kernel_ms": kms,
+        "kernel_tflops": flops / (kms * 1e-3) / 1e12,
+        "frac_of_fp64_peak": flops / (kms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS,
+        "kernel": "batched_kernel (all-minors tree per subset, persistent work list)"}
+    del bufs
+    inst = G.make_instance("grad_m144_k3")
+    s = torch.from_numpy(inst.sigma).to("cuda:0")
+    n = P.gbs_total_outputs(144, 3)
+    gk = torch.randn(n, dtype=torch.float64, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(5))
+    P.gbs_cumulant_grad(144, s, 3, 0, grad_cum=gk)
+    torch.cuda.synchronize()
+    walls, stages = [], None
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        P.gbs_cumulant_grad(144, s, 3, 0, grad_cum=gk)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    P.gbs_cumulant_grad(144, s, 3, P.GBS_TIMING, grad_cum=gk)
+    stages = {}
+    for st, order, ms in P.gbs_last_timings():
+        key = f"{st}{order}" if st != "build_q" else st
+        stages[key] = stages.get(key, 0.0) + ms
+    wall = sorted(walls)[len(walls) // 2]
+    out["grad_m144_k3"] = {"subsets": n, "ms_per_call": 1e3 * wall,
+                           "gradients_per_s": 1.0 / wall, "stage_ms": stages}
+    return out
+
+
 def cpu_baseline(np, O, G, inst, seconds):
     """The C oracle on the host cores over a random sample of the workload's
     subsets (all orders, in proportion to their counts)."""
@@ -169,6 +228,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and adjoint measurements")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -228,6 +289,8 @@ def main():
             del c64, k64
         if "fp64" in bufs and "mixed" in bufs:
             extra["mixed_error_vs_fp64"] = precision_errors(torch, P, *bufs["fp64"], *bufs["mixed"])
+    if not args.no_extras and not args.only:
+        extra["extras"] = batched_and_adjoint(P, torch, G, 5)
     base = None
     if not args.no_cpu_baseline:
         import oracle as O

@@ -116,6 +116,63 @@ def test_m144_k5_sampled(P, kernel):
     assert_within(cum[off + tail], rk, fp64_tolerance(rk, vkap), "tail cum")
 
 
+def _run_sampled(P, sigma, K, picks, flags=0):
+    """Run on the GPU and copy back only the outputs at picks[d] (ranks within order d)."""
+    import torch
+    M = sigma.shape[0] // 2
+    s = torch.from_numpy(np.ascontiguousarray(sigma)).to("cuda:0")
+    corr, cum = P.gbs_cumulants(M, s, K, flags)
+    torch.cuda.synchronize()
+    out = {}
+    for d, ranks in picks.items():
+        idx = torch.from_numpy(O.order_offset(M, d) + ranks).to("cuda:0")
+        out[d] = (corr[idx].cpu().numpy(), cum[idx].cpu().numpy())
+    del corr, cum
+    return out
+
+
+def _picks(M, K, n, seed, tail=200):
+    """Random ranks of every order plus the last `tail` ranks (the ragged end)."""
+    picks = {}
+    for d in range(1, K + 1):
+        cnt = math.comb(M, d)
+        r = G.random_ranks(cnt, min(n, cnt), seed=seed + d)
+        t = np.arange(max(0, cnt - tail), cnt, dtype=np.int64)
+        picks[d] = np.unique(np.concatenate([r, t]))
+    return picks
+
+
+@pytest.mark.parametrize("conv", [0, 1], ids=["click", "parity"])
+def test_tile_kernel_range(P, conv):
+    """M = 160, K = 4: orders 3 and 4 need more (T, a) records than the group
+    kernel holds (M - d + 1 > 148), so they run on the tile kernel."""
+    _say("case: M=160 K=4 sampled (tile kernel)", conv)
+    M, K = 160, 4
+    inst = G.make_instance("m144_k5", M=M, seed=31)
+    picks = _picks(M, K, 6000, 300)
+    got = _run_sampled(P, inst.sigma, K, picks, conv)
+    for d, ranks in picks.items():
+        rc, rk = O.c_forward_sample(inst.sigma, d, ranks, conv)
+        vmu, vkap = O.c_error_floor(inst.sigma, d, ranks, conv)
+        assert_within(got[d][0], rc, fp64_tolerance(rc, vmu), f"M=160 corr d={d}")
+        assert_within(got[d][1], rk, fp64_tolerance(rk, vkap), f"M=160 cum d={d}")
+
+
+def test_rec_kernel_64bit_ranks(P):
+    """M = 1500, K = 3: C(1500, 3) = 5.6e8 order-3 subsets exceed 2^29, so order 3
+    runs on the order-recursive kernel with 64-bit rank arithmetic."""
+    _say("case: M=1500 K=3 sampled (64-bit ranks)")
+    M, K = 1500, 3
+    inst = G.make_instance("m144_k5", M=M, seed=37)
+    picks = _picks(M, K, 3000, 400)
+    got = _run_sampled(P, inst.sigma, K, picks)
+    for d, ranks in picks.items():
+        rc, rk = O.c_forward_sample(inst.sigma, d, ranks)
+        vmu, vkap = O.c_error_floor(inst.sigma, d, ranks)
+        assert_within(got[d][0], rc, fp64_tolerance(rc, vmu), f"M=1500 corr d={d}")
+        assert_within(got[d][1], rk, fp64_tolerance(rk, vkap), f"M=1500 cum d={d}")
+
+
 def test_python_oracle_direct(P):
     """Same check against the Python tier of the oracle (fsum, library Cholesky)."""
     _say("case: M=9 K=5 python oracle")
