@@ -19,6 +19,12 @@ Conventions fixed here (the paper leaves them open):
 * Loss eta_k acts on input k before the interferometer, i.e. the transmission
   matrix is T = U diag(sqrt(eta)).  With uniform eta this is exactly
   sigma = eta S S^T / 2 + (1 - eta) I / 2 with S the squeezed interferometer.
+* Displaced inputs (first moments mu != 0, paper App. D.1 before Eq.
+  vacuum_gaussian_prob): input k is D(alpha_k) S(r_k)|0>, with |alpha_k|^2 drawn
+  uniformly from a stated range and a uniform phase; its mean is
+  sqrt(2) (Re alpha_k, Im alpha_k) (hbar = 1), and the lossy interferometer maps
+  input means linearly, mu = V mu_in with V the symplectic form of T.  The
+  covariance is unchanged by the displacement.
 """
 from __future__ import annotations
 
@@ -41,6 +47,9 @@ __all__ = [
     "random_ranks",
     "local_phase_rotation",
     "mode_permutation",
+    "input_displacement",
+    "DISPLACEMENT_SEED",
+    "DISPLACEMENT_AMP2",
 ]
 
 
@@ -107,6 +116,11 @@ WORKLOADS = {
                              note="adjoint, M=144, orders 1..3"),
 }
 GRAD_TARGET_SEED = 2511_1005
+# Displaced variant of a workload: same covariance, input amplitudes with
+# |alpha|^2 ~ U[0.05, 0.5] (0.02-0.2 displaced photons per mode after the
+# workloads' losses, small beside the squeezed photons).
+DISPLACEMENT_SEED = 2511_0006
+DISPLACEMENT_AMP2 = (0.05, 0.5)
 BATCH_COUNT = 48
 BATCH_M_RANGE = (40, 144)
 
@@ -218,3 +232,17 @@ def random_ranks(count_total: int, n: int, seed: int) -> np.ndarray:
     while len(picks) < n:
         picks.update(int(x) for x in rng.integers(0, count_total, size=n - len(picks)))
     return np.array(sorted(picks), dtype=np.int64)
+
+
+def input_displacement(inst: Instance, seed: int = DISPLACEMENT_SEED,
+                       amp2_range: tuple = DISPLACEMENT_AMP2) -> np.ndarray:
+    """Output first moments (xxpp, hbar = 1, length 2M) when input k of ``inst``
+    is displaced by alpha_k, |alpha_k|^2 ~ U[amp2_range], phase ~ U[0, 2 pi);
+    draw order: all |alpha|^2, then all phases."""
+    rng = np.random.default_rng(seed)
+    amp2 = rng.uniform(amp2_range[0], amp2_range[1], size=inst.M)
+    phase = rng.uniform(0.0, 2.0 * math.pi, size=inst.M)
+    alpha = np.sqrt(amp2) * np.exp(1j * phase)
+    mu_in = math.sqrt(2.0) * np.concatenate([alpha.real, alpha.imag])
+    V = interferometer_symplectic(inst.U * np.sqrt(inst.eta)[None, :])
+    return V @ mu_in

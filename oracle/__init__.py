@@ -11,6 +11,10 @@ Everything is plain FP64 and follows the paper's definitions directly:
   Q_T keeping rows/columns k and k+M for k in T (App. D.1, Eqs.
   vacuum_gaussian_prob and correlator_sum_cov with hbar = 1; the reduced-state
   rule is stated in the paragraph before Eq. vacuum_gaussian_prob);
+  for a displaced state with first moments mu (xxpp, length 2M) the same
+  equation gives p(T) = exp(-mu_T^T Q_T^{-1} mu_T / 2) det(Q_T)^(-1/2), mu_T
+  keeping entries k and k+M for k in T; every function taking ``mu`` uses it
+  (``mu=None`` is the zero-mean state);
 * click correlator (joint click moment) mu(S) = sum_{T subset S} (-1)^|T| p(T):
   the probability that every mode of S clicks (App. A.2, Eq. joint_moments_def,
   expanded with the threshold POVM of App. D.1);
@@ -145,13 +149,40 @@ def principal_block(Q: np.ndarray, T) -> np.ndarray:
     return Q[np.ix_(idx, idx)]
 
 
-def vacuum_probability(Q: np.ndarray, T) -> float:
-    """p(T) = det(Q_T)^(-1/2); p(empty) = 1.  The determinant is the squared
-    product of the Cholesky diagonal (library Cholesky)."""
+def principal_mean(mu: np.ndarray, T) -> np.ndarray:
+    """mu_T: entries k and k+M for k in T (xxpp), the first moments of the
+    reduced state (paragraph before Eq. vacuum_gaussian_prob)."""
+    M = len(mu) // 2
+    idx = [t for t in T] + [t + M for t in T]
+    return np.asarray(mu, dtype=np.float64)[idx]
+
+
+def mean_quadratic_form(Q: np.ndarray, mu: np.ndarray, T) -> float:
+    """mu_T^T Q_T^{-1} mu_T (library linear solve)."""
+    m = principal_mean(mu, T)
+    return float(m @ np.linalg.solve(principal_block(Q, T), m))
+
+
+def vacuum_probability(Q: np.ndarray, T, mu=None) -> float:
+    """p(T) = exp(-mu_T^T Q_T^{-1} mu_T / 2) det(Q_T)^(-1/2); p(empty) = 1
+    (Eq. vacuum_gaussian_prob, hbar = 1; mu=None is the zero-mean state).  The
+    determinant is the squared product of the Cholesky diagonal (library
+    Cholesky)."""
     if len(T) == 0:
         return 1.0
     L = np.linalg.cholesky(principal_block(Q, T))
-    return 1.0 / float(np.prod(np.diag(L)))
+    p = 1.0 / float(np.prod(np.diag(L)))
+    if mu is not None:
+        p *= math.exp(-0.5 * mean_quadratic_form(Q, mu, T))
+    return p
+
+
+def _vacuum_fn(Q, mu):
+    """T -> p(T) for the zero-mean (mu None) or the displaced state."""
+    if mu is None:
+        return lambda T: vacuum_probability(Q, T)
+    mu = np.asarray(mu, dtype=np.float64)
+    return lambda T: vacuum_probability(Q, T, mu)
 
 
 def all_subsets(S):
@@ -173,15 +204,16 @@ def parity_correlator(Q: np.ndarray, S, p=None) -> float:
     return (-1) ** len(S) * s
 
 
-def subset_values(sigma: np.ndarray, S, convention: int = CLICK) -> tuple:
+def subset_values(sigma: np.ndarray, S, convention: int = CLICK, mu=None) -> tuple:
     """(correlator, cumulant) of one subset S, computed from scratch."""
     Q = q_matrix(sigma)
     S = tuple(sorted(S))
     pcache = {}
+    vac = _vacuum_fn(Q, mu)
 
     def p(T):
         if T not in pcache:
-            pcache[T] = vacuum_probability(Q, T)
+            pcache[T] = vac(T)
         return pcache[T]
 
     corr_fn = click_correlator if convention == CLICK else parity_correlator
@@ -195,7 +227,8 @@ def subset_values(sigma: np.ndarray, S, convention: int = CLICK) -> tuple:
     return moment(S), cumulant_from_moments(S, moment)
 
 
-def correlators_and_cumulants(sigma: np.ndarray, K: int, convention: int = CLICK) -> tuple:
+def correlators_and_cumulants(sigma: np.ndarray, K: int, convention: int = CLICK,
+                              mu=None) -> tuple:
     """Full layout (all subsets of order 1..K) -> (corr, cum) FP64 arrays.
 
     Plain enumeration; p(T) of each distinct subset is evaluated once and
@@ -208,10 +241,11 @@ def correlators_and_cumulants(sigma: np.ndarray, K: int, convention: int = CLICK
     corr = np.empty(N)
     cum = np.empty(N)
     pcache = {}
+    vac = _vacuum_fn(Q, mu)
 
     def p(T):
         if T not in pcache:
-            pcache[T] = vacuum_probability(Q, T)
+            pcache[T] = vac(T)
         return pcache[T]
 
     corr_fn = click_correlator if convention == CLICK else parity_correlator
@@ -231,13 +265,13 @@ def correlators_and_cumulants(sigma: np.ndarray, K: int, convention: int = CLICK
     return corr, cum
 
 
-def sampled_values(sigma: np.ndarray, d: int, ranks, convention: int = CLICK) -> tuple:
+def sampled_values(sigma: np.ndarray, d: int, ranks, convention: int = CLICK, mu=None) -> tuple:
     """(corr, cum) for the order-d subsets with the given colex ranks."""
     ranks = np.asarray(ranks, dtype=np.int64)
     corr = np.empty(len(ranks))
     cum = np.empty(len(ranks))
     for i, r in enumerate(ranks):
-        corr[i], cum[i] = subset_values(sigma, colex_unrank(d, int(r)), convention)
+        corr[i], cum[i] = subset_values(sigma, colex_unrank(d, int(r)), convention, mu)
     return corr, cum
 
 
@@ -323,12 +357,14 @@ def pattern_probabilities(sigma: np.ndarray) -> np.ndarray:
 # high-precision arbiter (mpmath, 40 digits)
 
 
-def arbiter_values(sigma: np.ndarray, S, convention: int = CLICK, dps: int = 40) -> tuple:
+def arbiter_values(sigma: np.ndarray, S, convention: int = CLICK, dps: int = 40,
+                   mu=None) -> tuple:
     """(correlator, cumulant) of S with every step in dps-digit arithmetic.
 
-    sigma itself is taken as exact (its FP64 values); the result is accurate to
-    far better than FP64 rounding, so it settles disagreements between FP64
-    evaluations that round differently.
+    sigma (and mu) are taken as exact (their FP64 values); the result is
+    accurate to far better than FP64 rounding, so it settles disagreements
+    between FP64 evaluations that round differently.  For a displaced state
+    the quadratic form is |z|^2 with z = L^{-1} mu_T, L the Cholesky factor.
     """
     import mpmath as mp
 
@@ -362,6 +398,13 @@ def arbiter_values(sigma: np.ndarray, S, convention: int = CLICK, dps: int = 40)
                 else:
                     L[i][j] = s / L[j][j]
         pc[T] = 1 / det
+        if mu is not None:
+            # forward substitution L z = mu_T
+            z = []
+            for i in range(n):
+                v = ctx.mpf(float(mu[idx[i]])) - ctx.fsum(L[i][k] * z[k] for k in range(i))
+                z.append(v / L[i][i])
+            pc[T] *= ctx.exp(-ctx.fsum(v * v for v in z) / 2)
         return pc[T]
 
     def moment(B):
@@ -500,6 +543,12 @@ def _c():
         lib.oracle_loss_grad.restype = i32
         lib.oracle_error_floor.argtypes = [i32, dp, i32, lp, i64, i32, dp, dp, i32]
         lib.oracle_error_floor.restype = i32
+        lib.oracle_forward_mu.argtypes = [i32, dp, dp, i32, i32, dp, dp, i32]
+        lib.oracle_forward_mu.restype = i32
+        lib.oracle_forward_sample_mu.argtypes = [i32, dp, dp, i32, lp, i64, i32, dp, dp, i32]
+        lib.oracle_forward_sample_mu.restype = i32
+        lib.oracle_error_floor_mu.argtypes = [i32, dp, dp, i32, lp, i64, i32, dp, dp, i32]
+        lib.oracle_error_floor_mu.restype = i32
         lib.oracle_threads.argtypes = [i32]
         lib.oracle_threads.restype = i32
         _lib = lib
@@ -510,30 +559,44 @@ def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def _mu_arg(mu, M):
+    """(array kept alive, pointer) for an optional mean vector of length 2M."""
+    if mu is None:
+        return None, ctypes.POINTER(ctypes.c_double)()
+    mu = np.ascontiguousarray(mu, dtype=np.float64).reshape(-1)
+    if mu.shape[0] != 2 * M:
+        raise ValueError("mu must have 2M entries")
+    return mu, _dptr(mu)
+
+
 def c_threads(requested: int = 0) -> int:
     return int(_c().oracle_threads(requested))
 
 
-def c_forward(sigma: np.ndarray, K: int, convention: int = CLICK, threads: int = 0) -> tuple:
+def c_forward(sigma: np.ndarray, K: int, convention: int = CLICK, threads: int = 0,
+              mu=None) -> tuple:
     sigma = np.ascontiguousarray(sigma, dtype=np.float64)
     M = sigma.shape[0] // 2
     N = total_outputs(M, K)
     corr = np.empty(N)
     cum = np.empty(N)
-    rc = _c().oracle_forward(M, _dptr(sigma), K, convention, _dptr(corr), _dptr(cum), threads)
+    keep, mptr = _mu_arg(mu, M)
+    rc = _c().oracle_forward_mu(M, _dptr(sigma), mptr, K, convention, _dptr(corr), _dptr(cum),
+                                threads)
     if rc != 0:
         raise RuntimeError(f"oracle_forward failed ({rc})")
     return corr, cum
 
 
 def c_forward_sample(sigma: np.ndarray, d: int, ranks, convention: int = CLICK,
-                     threads: int = 0) -> tuple:
+                     threads: int = 0, mu=None) -> tuple:
     sigma = np.ascontiguousarray(sigma, dtype=np.float64)
     M = sigma.shape[0] // 2
     ranks = np.ascontiguousarray(ranks, dtype=np.int64)
     corr = np.empty(len(ranks))
     cum = np.empty(len(ranks))
-    rc = _c().oracle_forward_sample(M, _dptr(sigma), d,
+    keep, mptr = _mu_arg(mu, M)
+    rc = _c().oracle_forward_sample_mu(M, _dptr(sigma), mptr, d,
                                     ranks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                     len(ranks), convention, _dptr(corr), _dptr(cum), threads)
     if rc != 0:
@@ -559,7 +622,7 @@ FLOOR_FACTOR = 64.0
 
 
 def c_error_floor(sigma: np.ndarray, d: int, ranks, convention: int = CLICK,
-                  threads: int = 0) -> tuple:
+                  threads: int = 0, mu=None) -> tuple:
     """(vmu, vkap): magnitudes of the cancelling terms of each sampled output.
 
     An FP64 evaluation of mu(S) (or c(S)) sums terms of total magnitude vmu(S),
@@ -572,7 +635,8 @@ def c_error_floor(sigma: np.ndarray, d: int, ranks, convention: int = CLICK,
     ranks = np.ascontiguousarray(ranks, dtype=np.int64)
     vmu = np.empty(len(ranks))
     vkap = np.empty(len(ranks))
-    rc = _c().oracle_error_floor(M, _dptr(sigma), d,
+    keep, mptr = _mu_arg(mu, M)
+    rc = _c().oracle_error_floor_mu(M, _dptr(sigma), mptr, d,
                                  ranks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                  len(ranks), convention, _dptr(vmu), _dptr(vkap), threads)
     if rc != 0:

@@ -8,7 +8,9 @@
  *   p(T)  = det(Q_T)^(-1/2), Q = sigma + I/2, Q_T the rows/columns k, k+M for
  *           k in T (App. D.1, Eqs. vacuum_gaussian_prob, correlator_sum_cov,
  *           hbar = 1); the determinant is the squared product of a textbook
- *           Cholesky diagonal;
+ *           Cholesky diagonal.  With first moments mu (the *_mu entry points)
+ *           the same equation multiplies by exp(-|z|^2 / 2), z the forward
+ *           substitution L z = mu_T with the same Cholesky factor L;
  *   mu(S) = sum_{T subset S} (-1)^|T| p(T)            (App. A.2, joint moments)
  *   c(S)  = (-1)^|S| sum_{T subset S} (-2)^|T| p(T)   (Eq. corre_cov_main)
  *   cumulant(S) = sum over set partitions pi of S of
@@ -62,8 +64,10 @@ static void nadd(nsum* a, double x) {
 }
 static double nval(const nsum* a) { return a->s + a->c; }
 
-/* p(T) for the subset of S selected by mask; Q is 2M x 2M row-major */
-static int vacuum_prob(const double* Q, int M, const int* S, int d, unsigned mask, double* out) {
+/* p(T) for the subset of S selected by mask; Q is 2M x 2M row-major; mu is
+ * the 2M first moments (xxpp) or NULL for the zero-mean state */
+static int vacuum_prob(const double* Q, const double* mu, int M, const int* S, int d,
+                       unsigned mask, double* out) {
     int idx[NMAX];
     int n = 0;
     for (int k = 0; k < d; ++k) if (mask & (1u << k)) idx[n++] = S[k];
@@ -87,7 +91,19 @@ static int vacuum_prob(const double* Q, int M, const int* S, int d, unsigned mas
             A[i][j] = t / l;
         }
     }
-    *out = 1.0 / prod;
+    double e = 1.0;
+    if (mu) {
+        double z[NMAX];
+        double q = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double t = mu[idx[i]];
+            for (int k = 0; k < i; ++k) t -= A[i][k] * z[k];
+            z[i] = t / A[i][i];
+            q += z[i] * z[i];
+        }
+        e = exp(-0.5 * q);
+    }
+    *out = e / prod;
     return 0;
 }
 
@@ -129,13 +145,13 @@ static double weight(int nb) {
 static int popc(unsigned x) { int c = 0; while (x) { c += x & 1u; x >>= 1; } return c; }
 
 /* correlator and cumulant of one subset S (ascending, size d) */
-static int subset_values(const double* Q, int M, const int* S, int d, int convention,
-                         double* corr, double* cum) {
+static int subset_values(const double* Q, const double* mu, int M, const int* S, int d,
+                         int convention, double* corr, double* cum) {
     double p[1 << KMAX];
     double m[1 << KMAX];
     int full = (1 << d) - 1;
     for (unsigned T = 0; T <= (unsigned)full; ++T) {
-        int rc = vacuum_prob(Q, M, S, d, T, &p[T]);
+        int rc = vacuum_prob(Q, mu, M, S, d, T, &p[T]);
         if (rc) return rc;
     }
     for (unsigned B = 1; B <= (unsigned)full; ++B) {
@@ -187,8 +203,10 @@ int oracle_threads(int requested) {
 #endif
 }
 
-int oracle_forward_sample(int M, const double* sigma, int d, const int64_t* ranks, int64_t n,
-                          int convention, double* corr, double* cum, int threads) {
+/* mu: 2M first moments (xxpp), or NULL for the zero-mean state */
+int oracle_forward_sample_mu(int M, const double* sigma, const double* mu, int d,
+                             const int64_t* ranks, int64_t n, int convention, double* corr,
+                             double* cum, int threads) {
     if (M < 1 || d < 1 || d > KMAX || d > M) return 1;
     init_parts();
     oracle_threads(threads);
@@ -199,14 +217,19 @@ int oracle_forward_sample(int M, const double* sigma, int d, const int64_t* rank
     for (int64_t i = 0; i < n; ++i) {
         int S[KMAX];
         unrank(d, ranks[i], S);
-        err |= subset_values(Q, M, S, d, convention, &corr[i], &cum[i]);
+        err |= subset_values(Q, mu, M, S, d, convention, &corr[i], &cum[i]);
     }
     free(Q);
     return err;
 }
 
-int oracle_forward(int M, const double* sigma, int K, int convention, double* corr,
-                   double* cum, int threads) {
+int oracle_forward_sample(int M, const double* sigma, int d, const int64_t* ranks, int64_t n,
+                          int convention, double* corr, double* cum, int threads) {
+    return oracle_forward_sample_mu(M, sigma, NULL, d, ranks, n, convention, corr, cum, threads);
+}
+
+int oracle_forward_mu(int M, const double* sigma, const double* mu, int K, int convention,
+                      double* corr, double* cum, int threads) {
     if (M < 1 || K < 1 || K > KMAX || K > M) return 1;
     init_parts();
     oracle_threads(threads);
@@ -220,12 +243,17 @@ int oracle_forward(int M, const double* sigma, int K, int convention, double* co
         for (int64_t r = 0; r < cnt; ++r) {
             int S[KMAX];
             unrank(d, r, S);
-            err |= subset_values(Q, M, S, d, convention, &corr[off + r], &cum[off + r]);
+            err |= subset_values(Q, mu, M, S, d, convention, &corr[off + r], &cum[off + r]);
         }
         off += cnt;
     }
     free(Q);
     return err;
+}
+
+int oracle_forward(int M, const double* sigma, int K, int convention, double* corr,
+                   double* cum, int threads) {
+    return oracle_forward_mu(M, sigma, NULL, K, convention, corr, cum, threads);
 }
 
 /* inverse of the SPD matrix Q_T (n x n) by Gauss-Jordan without pivoting */
@@ -282,8 +310,8 @@ int oracle_loss_grad(int M, const double* sigma, int K, const double* target, do
             unrank(d, r, S);
             double c, k;
             double pv;
-            err |= vacuum_prob(Q, M, S, d, (1u << d) - 1, &pv);
-            err |= subset_values(Q, M, S, d, 0, &c, &k);
+            err |= vacuum_prob(Q, NULL, M, S, d, (1u << d) - 1, &pv);
+            err |= subset_values(Q, NULL, M, S, d, 0, &c, &k);
             p[off[d] + r] = pv;
             mu[off[d] + r] = c;
             kap[off[d] + r] = k;
@@ -372,8 +400,9 @@ done:
  *   vkap(S) = sum_pi |w(pi)| sum_{B in pi} vmu(B) prod_{B' in pi, B' != B} |m(B')|:
  *             the first-order propagation of those errors into the cumulant.
  */
-int oracle_error_floor(int M, const double* sigma, int d, const int64_t* ranks, int64_t n,
-                       int convention, double* vmu, double* vkap, int threads) {
+int oracle_error_floor_mu(int M, const double* sigma, const double* mu, int d,
+                          const int64_t* ranks, int64_t n, int convention, double* vmu,
+                          double* vkap, int threads) {
     if (M < 1 || d < 1 || d > KMAX || d > M) return 1;
     init_parts();
     oracle_threads(threads);
@@ -386,7 +415,7 @@ int oracle_error_floor(int M, const double* sigma, int d, const int64_t* ranks, 
         unrank(d, ranks[i], S);
         double p[1 << KMAX], m[1 << KMAX], v[1 << KMAX];
         int full = (1 << d) - 1;
-        for (unsigned T = 0; T <= (unsigned)full; ++T) err |= vacuum_prob(Q, M, S, d, T, &p[T]);
+        for (unsigned T = 0; T <= (unsigned)full; ++T) err |= vacuum_prob(Q, mu, M, S, d, T, &p[T]);
         for (unsigned B = 1; B <= (unsigned)full; ++B) {
             nsum acc = {0.0, 0.0};
             double mag = 0.0;
@@ -417,4 +446,9 @@ int oracle_error_floor(int M, const double* sigma, int d, const int64_t* ranks, 
     }
     free(Q);
     return err;
+}
+
+int oracle_error_floor(int M, const double* sigma, int d, const int64_t* ranks, int64_t n,
+                       int convention, double* vmu, double* vkap, int threads) {
+    return oracle_error_floor_mu(M, sigma, NULL, d, ranks, n, convention, vmu, vkap, threads);
 }

@@ -9,6 +9,7 @@ import pytest
 
 import gbs_inputs as G
 import oracle as O
+from fock import FockState, fock_cumulant, two_mode_state
 
 
 def _pin_single_mode():
@@ -141,7 +142,7 @@ def _mut_missing_vacuum(mp):
 
 
 def _mut_sqrt_missing(mp):
-    def vp(Q, T):
+    def vp(Q, T, mu=None):
         if len(T) == 0:
             return 1.0
         L = np.linalg.cholesky(O.principal_block(Q, T))
@@ -163,13 +164,127 @@ MUTATIONS = [_mut_weight_sign, _mut_weight_factorial, _mut_drop_full_term, _mut_
              _mut_partition_drop_singletons]
 
 
-@pytest.mark.parametrize("mutation", MUTATIONS, ids=lambda f: f.__name__)
-def test_mutation_is_caught(mutation, monkeypatch):
-    mutation(monkeypatch)
+def _run_battery(battery):
     results = []
-    for pin in BATTERY:
+    for pin in battery:
         try:
             results.append(bool(pin()))
         except (AssertionError, np.linalg.LinAlgError, ValueError, ZeroDivisionError):
             results.append(False)
-    assert not all(results), f"no pin caught {mutation.__name__}"
+    return results
+
+
+@pytest.mark.parametrize("mutation", MUTATIONS, ids=lambda f: f.__name__)
+def test_mutation_is_caught(mutation, monkeypatch):
+    mutation(monkeypatch)
+    assert not all(_run_battery(BATTERY)), f"no pin caught {mutation.__name__}"
+
+
+# ---------------------------------------------------------------------------
+# displaced states (Eq. vacuum_gaussian_prob with mu != 0)
+
+
+def _pin_coherent_product():
+    M = 4
+    rng = np.random.default_rng(5)
+    U = G.haar_unitary(M, rng)
+    alpha = rng.normal(size=M) + 1j * rng.normal(size=M)
+    mu = G.interferometer_symplectic(U) @ (math.sqrt(2.0) * np.concatenate([alpha.real, alpha.imag]))
+    corr, cum = O.correlators_and_cumulants(G.vacuum_covariance(M), 3, O.CLICK, mu)
+    f = 1.0 - np.exp(-np.abs(U @ alpha) ** 2)
+    ok = np.all(np.abs(cum[M:]) < 1e-13)
+    ok &= np.allclose(corr[:M], f, rtol=0, atol=1e-13)
+    return bool(ok)
+
+
+def _pin_fock_single():
+    st = FockState(1, 100)
+    st.squeeze(0, 0.6)
+    st.displace(0, 0.7 - 0.6j)
+    sigma, mu = st.moments()
+    corr, _ = O.correlators_and_cumulants(sigma, 1, O.CLICK, mu)
+    return abs(corr[0] - st.click_correlator((0,))) < 1e-12
+
+
+_FOCK = {}
+
+
+def _pin_fock_two_mode():
+    if "st" not in _FOCK:
+        _FOCK["st"] = two_mode_state()
+    st = _FOCK["st"]
+    sigma, mu = st.moments()
+    corr, cum = O.correlators_and_cumulants(sigma, 2, O.CLICK, mu)
+    pos = 0
+    for d in (1, 2):
+        for S in O.subsets_colex(2, d):
+            if abs(corr[pos] - st.click_correlator(S)) > 1e-12:
+                return False
+            if abs(cum[pos] - fock_cumulant(S, st.click_correlator)) > 1e-12:
+                return False
+            pos += 1
+    return True
+
+
+BATTERY_DISPLACED = [_pin_coherent_product, _pin_fock_single, _pin_fock_two_mode]
+
+
+def test_displaced_battery_passes_unmutated():
+    assert all(_run_battery(BATTERY_DISPLACED))
+
+
+def _mut_mean_xp_swapped(mp):
+    def pm(mu, T):
+        M = len(mu) // 2
+        return np.asarray(mu)[[t + M for t in T] + [t for t in T]]
+    mp.setattr(O, "principal_mean", pm)
+
+
+def _mut_mean_wrong_mode(mp):
+    def pm(mu, T):
+        M = len(mu) // 2
+        return np.asarray(mu)[[(t + 1) % M for t in T] + [(t + 1) % M + M for t in T]]
+    mp.setattr(O, "principal_mean", pm)
+
+
+def _mut_mean_missing_half(mp):
+    orig = O.mean_quadratic_form
+    mp.setattr(O, "mean_quadratic_form", lambda Q, mu, T: 2.0 * orig(Q, mu, T))
+
+
+def _mut_mean_sign(mp):
+    orig = O.mean_quadratic_form
+    mp.setattr(O, "mean_quadratic_form", lambda Q, mu, T: -orig(Q, mu, T))
+
+
+def _mut_mean_uses_sigma(mp):
+    def qf(Q, mu, T):
+        m = O.principal_mean(mu, T)
+        A = O.principal_block(Q, T) - 0.5 * np.eye(2 * len(T))
+        return float(m @ np.linalg.solve(A, m))
+    mp.setattr(O, "mean_quadratic_form", qf)
+
+
+def _mut_mean_diagonal_only(mp):
+    def qf(Q, mu, T):
+        m = O.principal_mean(mu, T)
+        return float(np.sum(m * m / np.diag(O.principal_block(Q, T))))
+    mp.setattr(O, "mean_quadratic_form", qf)
+
+
+def _mut_mean_not_inverted(mp):
+    def qf(Q, mu, T):
+        m = O.principal_mean(mu, T)
+        return float(m @ O.principal_block(Q, T) @ m)
+    mp.setattr(O, "mean_quadratic_form", qf)
+
+
+MUTATIONS_DISPLACED = [_mut_mean_xp_swapped, _mut_mean_wrong_mode, _mut_mean_missing_half,
+                       _mut_mean_sign, _mut_mean_uses_sigma, _mut_mean_diagonal_only,
+                       _mut_mean_not_inverted]
+
+
+@pytest.mark.parametrize("mutation", MUTATIONS_DISPLACED, ids=lambda f: f.__name__)
+def test_displaced_mutation_is_caught(mutation, monkeypatch):
+    mutation(monkeypatch)
+    assert not all(_run_battery(BATTERY_DISPLACED)), f"no pin caught {mutation.__name__}"
