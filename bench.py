@@ -26,6 +26,8 @@ K = 5
 # algorithmic flops per order-d subset: one new 2d x 2d factorisation, (2d)^3/3,
 # plus 2^(d+1) for inclusion-exclusion and the cumulant recursion
 FLOPS_PER_SUBSET = {d: (2 * d) ** 3 / 3 + 2 ** (d + 1) for d in range(1, 6)}
+# displaced states add one triangular solve of the mean, (2d)^2
+FLOPS_PER_SUBSET_DISP = {d: FLOPS_PER_SUBSET[d] + (2 * d) ** 2 for d in range(1, 6)}
 PEAK_VALU_TFLOPS = 78.6  # one non-packed FMA per lane per clock: 256 CU x 64 lanes x 2 x 2.4 GHz
 WORKLOAD = ("m144_k5: M=144 modes, subsets of order 1..5 (498,685,188), Haar interferometer, "
             "x-squeezing r~U[0.6,1.6], input loss eta~U[0.25,0.4], xxpp, hbar=1")
@@ -52,15 +54,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_precision(P, torch, sigma, corr, cum, flags, steps, warmup, label):
+def run_precision(P, torch, sigma, corr, cum, flags, steps, warmup, label, mu=None):
+    """Time `steps` calls of gbs_cumulants (or, with a mean vector mu,
+    gbs_cumulants_displaced) on resident buffers."""
+    def call(fl):
+        if mu is None:
+            P.gbs_cumulants(M, sigma, K, fl, corr=corr, cum=cum)
+        else:
+            P.gbs_cumulants_displaced(M, sigma, mu, K, fl, corr=corr, cum=cum)
+
     for i in range(warmup):
-        P.gbs_cumulants(M, sigma, K, flags, corr=corr, cum=cum)
+        call(flags)
         log(f"[bench] {label} warmup {i + 1}/{warmup} done")
     torch.cuda.synchronize()
     kern = {d: [] for d in range(1, K + 1)}
     t0 = time.perf_counter()
     for i in range(steps):
-        P.gbs_cumulants(M, sigma, K, flags | P.GBS_TIMING, corr=corr, cum=cum)
+        call(flags | P.GBS_TIMING)
         for stage, order, ms in P.gbs_last_timings():
             if stage == "forward":
                 kern[order].append(ms)
@@ -70,7 +80,7 @@ def run_precision(P, torch, sigma, corr, cum, flags, steps, warmup, label):
     ms_step = 1e3 * t / steps
     n = sum(math.comb(M, d) for d in range(1, K + 1))
     k5 = sum(kern[5]) / len(kern[5])
-    flops5 = math.comb(M, 5) * FLOPS_PER_SUBSET[5]
+    flops5 = math.comb(M, 5) * (FLOPS_PER_SUBSET if mu is None else FLOPS_PER_SUBSET_DISP)[5]
     return {
         "ms_per_step": ms_step,
         "subsets_per_s": n / (ms_step * 1e-3),
@@ -221,7 +231,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="which form gives the headline value (both are measured)")
-    ap.add_argument("--only", choices=["fp64", "mixed", "fp64_all_minors", "mixed_all_minors"],
+    ap.add_argument("--only", choices=["fp64", "mixed", "fp64_all_minors", "mixed_all_minors",
+                                       "displaced"],
                     default=None, help="measure one form only (profiling runs)")
     ap.add_argument("--all-minors", action="store_true",
                     help="also measure the all-minors kernel (GBS_ALL_MINORS) of both precisions")
@@ -266,12 +277,19 @@ def main():
     if args.all_minors and not args.only:
         forms += ["fp64_all_minors", "mixed_all_minors"]
     res, bufs = {}, {}
+    mu = None
+    if args.only == "displaced" or (not args.only and not args.no_extras):
+        # displaced variant of the same workload (seeded input amplitudes)
+        mu = torch.from_numpy(G.input_displacement(inst)).to("cuda:0")
+        if "displaced" not in forms:
+            forms.append("displaced")
     for form in forms:
         corr = torch.empty(N, dtype=torch.float64, device="cuda:0")
         cum = torch.empty(N, dtype=torch.float64, device="cuda:0")
         flags = (P.GBS_MIXED if form.startswith("mixed") else 0) | \
             (P.GBS_ALL_MINORS if form.endswith("all_minors") else 0)
-        res[form] = run_precision(P, torch, sigma, corr, cum, flags, args.steps, args.warmup, form)
+        res[form] = run_precision(P, torch, sigma, corr, cum, flags, args.steps, args.warmup, form,
+                                  mu=mu if form == "displaced" else None)
         if form in ("fp64", "mixed"):
             bufs[form] = (corr, cum)
         else:

@@ -8,7 +8,8 @@
  *
  * Problem (arXiv 2511.14923, Sec. I.A and App. D.1): sigma is the 2M x 2M
  * quadrature covariance of a zero-mean M-mode Gaussian state measured by
- * threshold detectors, hbar = 1 (vacuum = I/2).  With Q = sigma + I/2 and Q_T
+ * threshold detectors, hbar = 1 (vacuum = I/2); gbs_cumulants_displaced adds
+ * first moments.  With Q = sigma + I/2 and Q_T
  * the rows/columns k and k+M for k in T, the probability that every mode of T
  * is in vacuum is
  *        p(T) = det(Q_T)^(-1/2)          (Eqs. vacuum_gaussian_prob, correlator_sum_cov)
@@ -136,6 +137,23 @@ GBS_API gbs_status gbs_correlators(int32_t M, const double* sigma, int32_t max_o
  * Other arguments as gbs_correlators. */
 GBS_API gbs_status gbs_cumulants(int32_t M, const double* sigma, int32_t max_order, int32_t flags,
                          double* corr, double* cum, void* stream);
+
+/* Correlators and cumulants of a DISPLACED Gaussian state (first moments
+ * mu != 0).  The vacuum probability becomes
+ *        p(T) = exp(-mu_T^T Q_T^{-1} mu_T / 2) det(Q_T)^(-1/2)
+ * (App. D.1, Eq. vacuum_gaussian_prob, hbar = 1), with mu_T the entries k and
+ * k+M of mu for k in T; correlators and cumulants follow from p exactly as in
+ * gbs_cumulants.  mu = 0 gives gbs_cumulants' results (through a different
+ * kernel, so the last bits may differ).
+ *   mu     device, 2M FP64 first moments, xxpp order (index k is <x_k>, k+M is <p_k>)
+ *   flags  GBS_CLICK/GBS_PARITY | GBS_ASYNC | GBS_TIMING | GBS_ALL_MINORS;
+ *          GBS_MIXED gives GBS_E_UNSUPPORTED (FP64 only)
+ * Other arguments, layouts, ownership and errors as gbs_cumulants.  The
+ * default kernels are the order-recursive ones (one factorisation and one
+ * triangular solve of the mean per subset, lower orders read from tables). */
+GBS_API gbs_status gbs_cumulants_displaced(int32_t M, const double* sigma, const double* mu,
+                                   int32_t max_order, int32_t flags, double* corr, double* cum,
+                                   void* stream);
 
 /* Vector-Jacobian product of gbs_cumulants (FP64 only; GBS_MIXED gives
  * GBS_E_UNSUPPORTED):

@@ -41,7 +41,8 @@ GBS_MAX_MODES = 2048
 # every symbol declared in include/gbs.h
 EXPORTS = (
     "gbs_num_subsets", "gbs_order_offset", "gbs_total_outputs", "gbs_colex_rank",
-    "gbs_colex_unrank", "gbs_correlators", "gbs_cumulants", "gbs_cumulant_grad",
+    "gbs_colex_unrank", "gbs_correlators", "gbs_cumulants", "gbs_cumulants_displaced",
+    "gbs_cumulant_grad",
     "gbs_cumulants_batched", "gbs_autotune_batched", "gbs_set_tuning", "gbs_last_error",
     "gbs_last_timings", "gbs_status_string",
 )
@@ -97,6 +98,8 @@ def lib() -> ctypes.CDLL:
     L.gbs_correlators.restype = i32
     L.gbs_cumulants.argtypes = [i32, vp, i32, i32, vp, vp, vp]
     L.gbs_cumulants.restype = i32
+    L.gbs_cumulants_displaced.argtypes = [i32, vp, vp, i32, i32, vp, vp, vp]
+    L.gbs_cumulants_displaced.restype = i32
     L.gbs_cumulant_grad.argtypes = [i32, vp, i32, i32, vp, vp, vp, vp]
     L.gbs_cumulant_grad.restype = i32
     L.gbs_cumulants_batched.argtypes = [i32, ctypes.POINTER(gbs_instance), i32, i32, vp]
@@ -217,6 +220,20 @@ def gbs_cumulants(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0, c
         st = lib().gbs_cumulants(M, _ptr(sigma), max_order, flags, _ptr(corr), _ptr(cum),
                                  _stream(stream, sigma.device))
     _check(st, "gbs_cumulants")
+    return corr, cum
+
+
+def gbs_cumulants_displaced(M: int, sigma: torch.Tensor, mu: torch.Tensor, max_order: int,
+                            flags: int = 0, corr=None, cum=None, stream=None,
+                            want_corr: bool = True) -> tuple:
+    n = gbs_total_outputs(M, max_order)
+    if want_corr:
+        corr = _out(corr, max(n, 0), sigma)
+    cum = _out(cum, max(n, 0), sigma)
+    with torch.cuda.device(sigma.device):
+        st = lib().gbs_cumulants_displaced(M, _ptr(sigma), _ptr(mu), max_order, flags, _ptr(corr),
+                                           _ptr(cum), _stream(stream, sigma.device))
+    _check(st, "gbs_cumulants_displaced")
     return corr, cum
 
 

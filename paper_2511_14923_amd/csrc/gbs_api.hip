@@ -126,6 +126,7 @@ bool valid_problem(int32_t M, int32_t K, int32_t flags) {
 struct ForwardScratch {
   double* Qi;
   double* Qd;
+  double* mi;  // interleaved first moments (displaced states), else null
   double* pk;
   float* E;
   DeviceStatus* st;
@@ -134,7 +135,7 @@ struct ForwardScratch {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-ForwardScratch layout_scratch(char* base, int M, bool mixed) {
+ForwardScratch layout_scratch(char* base, int M, bool mixed, bool displaced) {
   ForwardScratch s{};
   size_t off = 0;
   const size_t nq = 4 * (size_t)M * M;
@@ -142,6 +143,12 @@ ForwardScratch layout_scratch(char* base, int M, bool mixed) {
   off += align256(nq * sizeof(double));
   s.Qd = reinterpret_cast<double*>(base + off);
   off += align256(4 * (size_t)M * sizeof(double));
+  if (displaced) {
+    s.mi = reinterpret_cast<double*>(base + off);
+    off += align256(2 * (size_t)M * sizeof(double));
+  } else {
+    s.mi = nullptr;
+  }
   if (mixed) {
     s.pk = reinterpret_cast<double*>(base + off);
     off += align256((size_t)M * sizeof(double));
@@ -208,22 +215,23 @@ gbs_status finish_call(DeviceStatus* dev_status, void* scratch, int32_t flags, h
   return status_wait(flags, s);
 }
 
-gbs_status run_forward(int32_t M, const double* sigma, int32_t K, int32_t flags, double* corr,
-                       double* cum, void* stream) {
+// mu: device first moments (2M, xxpp) of a displaced state, or null.
+gbs_status run_forward(int32_t M, const double* sigma, const double* mu, int32_t K, int32_t flags,
+                       double* corr, double* cum, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e;
   DeviceContext* ctx = current_context(&e);
   if (!ctx) return to_status(e);
   const bool mixed = (flags & GBS_MIXED) != 0;
   const bool rec = !(flags & GBS_ALL_MINORS);
-  ForwardScratch probe = layout_scratch(nullptr, M, mixed);
+  ForwardScratch probe = layout_scratch(nullptr, M, mixed, mu != nullptr);
   // lower-order tables of the recursive kernel: p always, m when corr is NULL
   const size_t nlow = K >= 2 ? (size_t)gbs_order_offset(M, K) : 0;
   const size_t tab_bytes = rec ? align256(nlow * sizeof(double)) * (corr ? 1 : 2) : 0;
   void* scratch = nullptr;
   e = hipMallocAsync(&scratch, probe.bytes + tab_bytes, s);
   if (e != hipSuccess) return to_status(e);
-  ForwardScratch sc = layout_scratch(static_cast<char*>(scratch), M, mixed);
+  ForwardScratch sc = layout_scratch(static_cast<char*>(scratch), M, mixed, mu != nullptr);
   double* ptab = reinterpret_cast<double*>(static_cast<char*>(scratch) + probe.bytes);
   double* mtab = corr ? corr : ptab + align256(nlow * sizeof(double)) / sizeof(double);
   t_err.order = 0;
@@ -233,6 +241,7 @@ gbs_status run_forward(int32_t M, const double* sigma, int32_t K, int32_t flags,
   if (e == hipSuccess) e = timing_begin(s, GBS_STAGE_BUILD_Q, 0);
   if (e == hipSuccess) e = launch_build_q(sigma, M, sc.Qi, s);
   if (e == hipSuccess) e = launch_build_qdiag(sc.Qi, M, sc.Qd, s);
+  if (e == hipSuccess && mu) e = launch_build_mean(mu, M, sc.mi, s);
   if (e == hipSuccess) e = timing_end(s);
   if (e == hipSuccess && mixed) {
     e = timing_begin(s, GBS_STAGE_NORMALISE, 0);
@@ -250,13 +259,14 @@ gbs_status run_forward(int32_t M, const double* sigma, int32_t K, int32_t flags,
       double* m_out = (corr || d < K) ? mtab + off : nullptr;
       double* k_out = cum ? cum + off : nullptr;
       double* p_out = d < K ? ptab + off : nullptr;
-      e = launch_forward_rec(d, M, flags, sc.Qi, sc.Qd, sc.pk, sc.E, ctx->binom, p_tab, m_tab,
+      e = launch_forward_rec(d, M, flags, sc.Qi, sc.Qd, sc.mi, sc.pk, sc.E, ctx->binom, p_tab, m_tab,
                              k_tab, m_out, k_out, p_out, sc.st, s);
       p_tab[d] = ptab + off;
       m_tab[d] = mtab + off;
       k_tab[d] = cum ? cum + off : nullptr;
     } else {
-      e = launch_forward(d, M, flags, sc.Qi, sc.pk, sc.E, ctx->binom, corr ? corr + off : nullptr,
+      e = launch_forward(d, M, flags, sc.Qi, sc.mi, sc.pk, sc.E, ctx->binom,
+                         corr ? corr + off : nullptr,
                          cum ? cum + off : nullptr, nullptr, sc.st, s);
     }
     if (e == hipSuccess) e = timing_end(s);
@@ -312,7 +322,7 @@ gbs_status run_adjoint(int32_t M, const double* sigma, int32_t K, int32_t flags,
     const int64_t o = gbs_order_offset(M, d);
     e = timing_begin(s, GBS_STAGE_FORWARD, d);
     if (e == hipSuccess)
-      e = launch_forward_rec(d, M, flags & GBS_PARITY, Qi, Qd, nullptr, nullptr, ctx->binom,
+      e = launch_forward_rec(d, M, flags & GBS_PARITY, Qi, Qd, nullptr, nullptr, nullptr, ctx->binom,
                              p_tab, m_tab, k_tab, m + o, nullptr, ptab + o, st, s);
     p_tab[d] = ptab + o;
     m_tab[d] = m + o;
@@ -390,13 +400,21 @@ gbs_status gbs_colex_unrank(int32_t d, int64_t r, int32_t* S) {
 gbs_status gbs_correlators(int32_t M, const double* sigma, int32_t max_order, int32_t flags,
                            double* corr, void* stream) {
   if (!valid_problem(M, max_order, flags) || !sigma || !corr) return GBS_E_INVALID_ARG;
-  return run_forward(M, sigma, max_order, flags, corr, nullptr, stream);
+  return run_forward(M, sigma, nullptr, max_order, flags, corr, nullptr, stream);
 }
 
 gbs_status gbs_cumulants(int32_t M, const double* sigma, int32_t max_order, int32_t flags,
                          double* corr, double* cum, void* stream) {
   if (!valid_problem(M, max_order, flags) || !sigma || !cum) return GBS_E_INVALID_ARG;
-  return run_forward(M, sigma, max_order, flags, corr, cum, stream);
+  return run_forward(M, sigma, nullptr, max_order, flags, corr, cum, stream);
+}
+
+gbs_status gbs_cumulants_displaced(int32_t M, const double* sigma, const double* mu,
+                                   int32_t max_order, int32_t flags, double* corr, double* cum,
+                                   void* stream) {
+  if (!valid_problem(M, max_order, flags) || !sigma || !mu || !cum) return GBS_E_INVALID_ARG;
+  if (flags & GBS_MIXED) return GBS_E_UNSUPPORTED;
+  return run_forward(M, sigma, mu, max_order, flags, corr, cum, stream);
 }
 
 gbs_status gbs_cumulant_grad(int32_t M, const double* sigma, int32_t max_order, int32_t flags,

@@ -106,6 +106,37 @@ __device__ __forceinline__ void schur_leading_block(const Tri<n>& A, double inv_
   }
 }
 
+// Displaced states: the share of mu^T Q^{-1} mu taken by the leading 2x2 pivot
+// P of A, given the mean v over A's rows (v[0..1] on P):
+//   w = P^{-1} v_P,  returns v_P . w,  vr[i - 2] = v[i] - A_{i,P} w  (i >= 2),
+// so vr is the mean over the rows of the Schur complement A / P and the
+// quadratic form splits as v_P^T P^{-1} v_P + vr^T (A / P)^{-1} vr (block
+// elimination of the bordered matrix [[A, v], [v^T, 0]]).  inv_det = 1/det(P).
+template <int n>
+__device__ __forceinline__ double pivot_mean(const Tri<n>& A, double inv_det, const double* v,
+                                             double* vr) {
+  const double a00 = A.a[0], a10 = A.a[1], a11 = A.a[2];
+  const double w0 = fma(a11, v[0], -a10 * v[1]) * inv_det;
+  const double w1 = fma(a00, v[1], -a10 * v[0]) * inv_det;
+#pragma unroll
+  for (int i = 2; i < n; ++i)
+    vr[i - 2] = fma(-A.a[tri(i, 1)], w1, fma(-A.a[tri(i, 0)], w0, v[i]));
+  return fma(v[0], w0, v[1] * w1);
+}
+
+// The first moments of modes s[0..n-1] (in the given order) from the
+// interleaved mean vector (x_k at 2k, p_k at 2k+1).
+template <int n>
+__device__ __forceinline__ void gather_mean(const double* __restrict__ mi, const int* s,
+                                            double (&v)[2 * n]) {
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    const double2 m = *reinterpret_cast<const double2*>(mi + 2 * (size_t)s[i]);
+    v[2 * i] = m.x;
+    v[2 * i + 1] = m.y;
+  }
+}
+
 // Gather the 2n x 2n principal block of the interleaved Q for modes s[0..n-1]
 // (in the given order: block i of the result is mode s[i]).
 template <int n>

@@ -21,6 +21,9 @@
 //      correlators_expanded_2; equivalent to the partition sum of Eq.
 //      cumulant_corr_main / joint_cumulants_def);
 //   6. stores the correlator and the cumulant of S at its colex rank.
+// For a displaced state (first moments mu) the recursion also carries the mean
+// reduced by the eliminated blocks, and every p(T) gains
+// exp(-mu_T^T Q_T^{-1} mu_T / 2) (Eq. vacuum_gaussian_prob).
 #include <hip/hip_runtime.h>
 
 #include "gbs_internal.h"
@@ -28,8 +31,9 @@
 
 namespace gbs {
 
-template <int D, int CONV, bool WRITE_CORR, bool WRITE_CUM, bool LDS_BIN>
-__global__ __launch_bounds__(256) void forward_fp64_kernel(const double* __restrict__ Qi, int M,
+template <int D, int CONV, bool WRITE_CORR, bool WRITE_CUM, bool LDS_BIN, bool DISP>
+__global__ __launch_bounds__(256) void forward_fp64_kernel(const double* __restrict__ Qi,
+                                                           const double* __restrict__ mi, int M,
                                                            uint64_t count,
                                                            const uint64_t* __restrict__ binom,
                                                            double* __restrict__ corr,
@@ -58,7 +62,8 @@ __global__ __launch_bounds__(256) void forward_fp64_kernel(const double* __restr
   colex_unrank<D>(r, M, bin, ld, s);
   double mS, kS, pS;
   bool bad = false;
-  subset_fp64<D, CONV, WRITE_CUM>(Qi, M, s, mS, kS, pS, bad);
+  if constexpr (DISP) subset_fp64_disp<D, CONV, WRITE_CUM>(Qi, mi, M, s, mS, kS, pS, bad);
+  else subset_fp64<D, CONV, WRITE_CUM>(Qi, M, s, mS, kS, pS, bad);
   if (bad) latch_failure(st, D, (int64_t)r);
   if (ptab) ptab[r] = pS;
   if constexpr (WRITE_CORR) corr[r] = mS;
@@ -113,60 +118,86 @@ hipError_t launch_build_q(const double* sigma, int M, double* Qi, hipStream_t s)
   return hipGetLastError();
 }
 
+// First moments in interleaved order: mi[2k] = mu[k] (x_k), mi[2k+1] = mu[k+M] (p_k).
+__global__ void build_mean_kernel(const double* __restrict__ mu, int M, double* __restrict__ mi) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  mi[2 * (size_t)k] = mu[k];
+  mi[2 * (size_t)k + 1] = mu[(size_t)k + M];
+}
+
+hipError_t launch_build_mean(const double* mu, int M, double* mi, hipStream_t s) {
+  hipLaunchKernelGGL(build_mean_kernel, dim3((M + 255) / 256), dim3(256), 0, s, mu, M, mi);
+  return hipGetLastError();
+}
+
 hipError_t launch_clear_status(DeviceStatus* st, hipStream_t s) {
   hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(1), 0, s, st);
   return hipGetLastError();
 }
 
-template <int D, int CONV, bool WC, bool WK>
-static hipError_t launch_fp64_t(int M, const double* Qi, const uint64_t* binom, double* corr,
-                                double* cum, double* ptab, DeviceStatus* st, hipStream_t s) {
+template <int D, int CONV, bool WC, bool WK, bool DISP>
+static hipError_t launch_fp64_t(int M, const double* Qi, const double* mi, const uint64_t* binom,
+                                double* corr, double* cum, double* ptab, DeviceStatus* st,
+                                hipStream_t s) {
   const uint64_t count = host_binom(M, D);
   if (count == 0) return hipSuccess;
   const int block = 256;
   const uint64_t grid = std::min<uint64_t>((count + block - 1) / block, kMaxGrid);
   const size_t lds = (size_t)(D + 1) * (M + 1) * sizeof(uint64_t);
   if (lds <= 48 * 1024) {
-    hipLaunchKernelGGL((forward_fp64_kernel<D, CONV, WC, WK, true>), dim3((unsigned)grid),
-                       dim3(block), lds, s, Qi, M, count, binom, corr, cum, ptab, st);
+    hipLaunchKernelGGL((forward_fp64_kernel<D, CONV, WC, WK, true, DISP>), dim3((unsigned)grid),
+                       dim3(block), lds, s, Qi, mi, M, count, binom, corr, cum, ptab, st);
   } else {
-    hipLaunchKernelGGL((forward_fp64_kernel<D, CONV, WC, WK, false>), dim3((unsigned)grid),
-                       dim3(block), 0, s, Qi, M, count, binom, corr, cum, ptab, st);
+    hipLaunchKernelGGL((forward_fp64_kernel<D, CONV, WC, WK, false, DISP>), dim3((unsigned)grid),
+                       dim3(block), 0, s, Qi, mi, M, count, binom, corr, cum, ptab, st);
   }
   return hipGetLastError();
 }
 
-template <int D, int CONV>
-static hipError_t launch_fp64_w(int M, const double* Qi, const uint64_t* binom, double* corr,
-                                double* cum, double* ptab, DeviceStatus* st, hipStream_t s) {
-  if (corr && cum) return launch_fp64_t<D, CONV, true, true>(M, Qi, binom, corr, cum, ptab, st, s);
-  if (corr) return launch_fp64_t<D, CONV, true, false>(M, Qi, binom, corr, cum, ptab, st, s);
-  return launch_fp64_t<D, CONV, false, true>(M, Qi, binom, corr, cum, ptab, st, s);
+template <int D, int CONV, bool DISP>
+static hipError_t launch_fp64_w(int M, const double* Qi, const double* mi, const uint64_t* binom,
+                                double* corr, double* cum, double* ptab, DeviceStatus* st,
+                                hipStream_t s) {
+  if (corr && cum)
+    return launch_fp64_t<D, CONV, true, true, DISP>(M, Qi, mi, binom, corr, cum, ptab, st, s);
+  if (corr)
+    return launch_fp64_t<D, CONV, true, false, DISP>(M, Qi, mi, binom, corr, cum, ptab, st, s);
+  return launch_fp64_t<D, CONV, false, true, DISP>(M, Qi, mi, binom, corr, cum, ptab, st, s);
 }
 
 template <int D>
-static hipError_t launch_fp64_c(int M, int flags, const double* Qi, const uint64_t* binom,
-                                double* corr, double* cum, double* ptab, DeviceStatus* st,
-                                hipStream_t s) {
-  if (flags & GBS_PARITY) return launch_fp64_w<D, GBS_PARITY>(M, Qi, binom, corr, cum, ptab, st, s);
-  return launch_fp64_w<D, GBS_CLICK>(M, Qi, binom, corr, cum, ptab, st, s);
+static hipError_t launch_fp64_c(int M, int flags, const double* Qi, const double* mi,
+                                const uint64_t* binom, double* corr, double* cum, double* ptab,
+                                DeviceStatus* st, hipStream_t s) {
+  if (mi) {
+    if (flags & GBS_PARITY)
+      return launch_fp64_w<D, GBS_PARITY, true>(M, Qi, mi, binom, corr, cum, ptab, st, s);
+    return launch_fp64_w<D, GBS_CLICK, true>(M, Qi, mi, binom, corr, cum, ptab, st, s);
+  }
+  if (flags & GBS_PARITY)
+    return launch_fp64_w<D, GBS_PARITY, false>(M, Qi, mi, binom, corr, cum, ptab, st, s);
+  return launch_fp64_w<D, GBS_CLICK, false>(M, Qi, mi, binom, corr, cum, ptab, st, s);
 }
 
 hipError_t launch_forward_mixed(int d, int M, int flags, const double* pk, const float* E,
                                 const uint64_t* binom, double* corr, double* cum,
                                 DeviceStatus* st, hipStream_t s);
 
-hipError_t launch_forward(int d, int M, int flags, const double* Qi, const double* pk,
-                          const float* E, const uint64_t* binom, double* corr, double* cum,
-                          double* ptab, DeviceStatus* st, hipStream_t s) {
+hipError_t launch_forward(int d, int M, int flags, const double* Qi, const double* mi,
+                          const double* pk, const float* E, const uint64_t* binom, double* corr,
+                          double* cum, double* ptab, DeviceStatus* st, hipStream_t s) {
   if (!corr && !cum) return hipSuccess;
-  if (flags & GBS_MIXED) return launch_forward_mixed(d, M, flags, pk, E, binom, corr, cum, st, s);
+  if (flags & GBS_MIXED) {
+    if (mi) return hipErrorInvalidValue;
+    return launch_forward_mixed(d, M, flags, pk, E, binom, corr, cum, st, s);
+  }
   switch (d) {
-    case 1: return launch_fp64_c<1>(M, flags, Qi, binom, corr, cum, ptab, st, s);
-    case 2: return launch_fp64_c<2>(M, flags, Qi, binom, corr, cum, ptab, st, s);
-    case 3: return launch_fp64_c<3>(M, flags, Qi, binom, corr, cum, ptab, st, s);
-    case 4: return launch_fp64_c<4>(M, flags, Qi, binom, corr, cum, ptab, st, s);
-    case 5: return launch_fp64_c<5>(M, flags, Qi, binom, corr, cum, ptab, st, s);
+    case 1: return launch_fp64_c<1>(M, flags, Qi, mi, binom, corr, cum, ptab, st, s);
+    case 2: return launch_fp64_c<2>(M, flags, Qi, mi, binom, corr, cum, ptab, st, s);
+    case 3: return launch_fp64_c<3>(M, flags, Qi, mi, binom, corr, cum, ptab, st, s);
+    case 4: return launch_fp64_c<4>(M, flags, Qi, mi, binom, corr, cum, ptab, st, s);
+    case 5: return launch_fp64_c<5>(M, flags, Qi, mi, binom, corr, cum, ptab, st, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -27,6 +27,11 @@
 //      (the partition sum of Eq. cumulant_corr_main grouped by the block that
 //      contains e; App. B, Eq. correlators_expanded_2); Y = {a} + B' gives k(S);
 //   5. stores m(S), k(S) and, below the last order, p(S).
+// For a displaced state (first moments mu) the factorisation also carries the
+// mean reduced by the eliminated blocks: each pivot adds its share of
+// mu_T^T Q_T^{-1} mu_T (pivot_mean), and the four probabilities of step 2 gain
+// exp(-mu_T^T Q_T^{-1} mu_T / 2) (Eq. vacuum_gaussian_prob); the tables of the
+// lower orders already hold displaced values, so steps 3-5 are unchanged.
 // Every output thus costs one 2d x 2d factorisation plus O(2^d) additions --
 // the work count of the method's cost model.  A capped grid of workgroups
 // strides over the ranks, so each workgroup fills its LDS binomial table once.
@@ -39,52 +44,90 @@ namespace gbs {
 // Workgroups of a launch; each strides over many subsets.
 constexpr uint64_t kRecGrid = 4096;
 
+// Quadratic-form shares of a displaced state, accumulated beside the
+// determinant products of the chains below (unused, and removed by the
+// compiler, for a zero-mean state).
+struct MeanForms {
+  double de = 0.0, d = 0.0, a = 0.0, s = 0.0;  // mu_T^T Q_T^{-1} mu_T for the four T
+};
+
 // Leading-block elimination chain for the block order [.., a, d, e]: multiplies
 // P by det(pivot)^(-1/2) for each block; pDE receives the product before d
 // (p(S \ {d, e})), pD the product times the e block of the Schur complement
 // at that point (p(S \ {d})), pA the product before e (p(S \ {e})), pS the
-// full product.
-template <int n>
-__device__ __forceinline__ void chain2(const Tri<n>& A, double P, double& pDE, double& pD,
-                                       double& pA, double& pS, bool& bad) {
+// full product.  With DISP, v is the mean over A's rows, q the quadratic form
+// of the blocks eliminated so far, and qf receives the same four quantities
+// for mu_T^T Q_T^{-1} mu_T.
+template <int n, bool DISP>
+__device__ __forceinline__ void chain2(const Tri<n>& A, const double (&v)[n], double P, double q,
+                                       double& pDE, double& pD, double& pA, double& pS,
+                                       MeanForms& qf, bool& bad) {
   if constexpr (n == 4) {
     pDE = P;
     // e block of the 4x4 Schur complement
     const double e00 = A.a[tri(2, 2)], e10 = A.a[tri(3, 2)], e11 = A.a[tri(3, 3)];
     const double dete = fma(e00, e11, -e10 * e10);
     bad |= !(dete > 0.0);
-    pD = P * rsqrt_f64(dete);
+    const double ye = rsqrt_f64(dete);
+    pD = P * ye;
+    if constexpr (DISP) {
+      qf.de = q;
+      // v_e^T E^{-1} v_e with E^{-1} = adj(E) / det(E)
+      const double t = fma(e11 * v[2], v[2], fma(-2.0 * e10 * v[2], v[3], e00 * v[3] * v[3]));
+      qf.d = fma(t, ye * ye, q);
+    }
   }
   const double a00 = A.a[0], a10 = A.a[1], a11 = A.a[2];
   const double det = fma(a00, a11, -a10 * a10);
   bad |= !(a00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
   const double y = rsqrt_f64(det);
   const double Pn = P * y;
+  double vr[n > 2 ? n - 2 : 1];
+  double qn = q;
+  if constexpr (DISP) qn += pivot_mean<n>(A, y * y, v, vr);
   if constexpr (n == 2) {
     pS = Pn;
+    if constexpr (DISP) qf.s = qn;
   } else {
-    if constexpr (n == 4) pA = Pn;
+    if constexpr (n == 4) {
+      pA = Pn;
+      if constexpr (DISP) qf.a = qn;
+    }
     Tri<n - 2> S;
     schur_leading_block<n>(A, y * y, S);
-    chain2<n - 2>(S, Pn, pDE, pD, pA, pS, bad);
+    double vs[n - 2];
+#pragma unroll
+    for (int i = 0; i < n - 2; ++i) vs[i] = DISP ? vr[i] : 0.0;
+    chain2<n - 2, DISP>(S, vs, Pn, qn, pDE, pD, pA, pS, qf, bad);
   }
 }
 
 // The same for the block order [.., a, e]: pA = p(S \ {e}), pS = p(S).
-template <int n, int NB>
-__device__ __forceinline__ void chain(const Tri<n>& A, double P, double& pA, double& pS, bool& bad) {
+template <int n, int NB, bool DISP>
+__device__ __forceinline__ void chain(const Tri<n>& A, const double (&v)[n], double P, double q,
+                                      double& pA, double& pS, MeanForms& qf, bool& bad) {
   const double a00 = A.a[0], a10 = A.a[1], a11 = A.a[2];
   const double det = fma(a00, a11, -a10 * a10);
   bad |= !(a00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
   const double y = rsqrt_f64(det);
   const double Pn = P * y;
+  double vr[n > 2 ? n - 2 : 1];
+  double qn = q;
+  if constexpr (DISP) qn += pivot_mean<n>(A, y * y, v, vr);
   if constexpr (n == 2) {
     pS = Pn;
+    if constexpr (DISP) qf.s = qn;
   } else {
-    if constexpr (n == 4) pA = Pn;
+    if constexpr (n == 4) {
+      pA = Pn;
+      if constexpr (DISP) qf.a = qn;
+    }
     Tri<n - 2> S;
     schur_leading_block<n>(A, y * y, S);
-    chain<n - 2, NB>(S, Pn, pA, pS, bad);
+    double vs[n - 2];
+#pragma unroll
+    for (int i = 0; i < n - 2; ++i) vs[i] = DISP ? vr[i] : 0.0;
+    chain<n - 2, NB, DISP>(S, vs, Pn, qn, pA, pS, qf, bad);
   }
 }
 
@@ -127,9 +170,10 @@ __device__ __forceinline__ void chain_dev(const TriF<n>& F, float rho, float& rh
   }
 }
 
-template <int D, int CONV, bool WANT_CUM, bool LDS_BIN, typename Idx, bool MIXED>
+template <int D, int CONV, bool WANT_CUM, bool LDS_BIN, typename Idx, bool MIXED, bool DISP>
 __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restrict__ Qi,
                                                           const double* __restrict__ Qd,
+                                                          const double* __restrict__ mi,
                                                           const double* __restrict__ pk,
                                                           const float* __restrict__ E, int M,
                                                           uint64_t count,
@@ -140,6 +184,7 @@ __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restri
                                                           double* __restrict__ p_out,
                                                           DeviceStatus* __restrict__ st) {
   static_assert(D >= 2 && D <= kMaxOrder, "orders 2..5");
+  static_assert(!(MIXED && DISP), "displaced states are FP64 only");
   constexpr int NB = D - 1;          // |B|
   constexpr int NU = 1 << NB;        // subsets of B
   constexpr int FULL = NU - 1;       // B
@@ -232,8 +277,17 @@ __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restri
       ch[D - 1] = e;
       Tri<2 * D> A;
       gather_q_coalesced<D, D - 3>(Qi, Qd, M, ch, A);
+      double v[2 * D] = {};
+      if constexpr (DISP) gather_mean<D>(mi, ch, v);
       double pDE = 1.0, pD = 1.0;
-      chain2<2 * D>(A, 1.0, pDE, pD, pA, pS, bad);
+      MeanForms qf;
+      chain2<2 * D, DISP>(A, v, 1.0, 0.0, pDE, pD, pA, pS, qf, bad);
+      if constexpr (DISP) {
+        pDE *= exp(-0.5 * qf.de);
+        pD *= exp(-0.5 * qf.d);
+        pA *= exp(-0.5 * qf.a);
+        pS *= exp(-0.5 * qf.s);
+      }
       if constexpr (UDROP_D >= 0) {
         pu[UDROP_D] = pD;
         pu[UDROP_DE] = pDE;
@@ -246,7 +300,14 @@ __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restri
       ch[D - 1] = e;
       Tri<2 * D> A;
       gather_q_coalesced<D, D - 2>(Qi, Qd, M, ch, A);
-      chain<2 * D, D>(A, 1.0, pA, pS, bad);
+      double v[2 * D] = {};
+      if constexpr (DISP) gather_mean<D>(mi, ch, v);
+      MeanForms qf;
+      chain<2 * D, D, DISP>(A, v, 1.0, 0.0, pA, pS, qf, bad);
+      if constexpr (DISP) {
+        pA *= exp(-0.5 * qf.a);
+        pS *= exp(-0.5 * qf.s);
+      }
     }
     if (bad) latch_failure(st, D, (int64_t)r);
     pu[FULL] = pS;
@@ -328,10 +389,12 @@ __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restri
   }
 }
 
-// Order 1: p({a}) = det(Q_aa)^(-1/2), mu = 1 - p (click) or c = 2p - 1 (parity),
-// and the cumulant of a single mode is its correlator.
-template <int CONV>
-__global__ void forward_order1_kernel(const double* __restrict__ Qi, int M, double* __restrict__ m_out,
+// Order 1: p({a}) = det(Q_aa)^(-1/2) (times exp(-v^T Q_aa^{-1} v / 2) for a
+// displaced state with mean v on mode a), mu = 1 - p (click) or c = 2p - 1
+// (parity), and the cumulant of a single mode is its correlator.
+template <int CONV, bool DISP>
+__global__ void forward_order1_kernel(const double* __restrict__ Qi, const double* __restrict__ mi,
+                                      int M, double* __restrict__ m_out,
                                       double* __restrict__ k_out, double* __restrict__ p_out,
                                       DeviceStatus* __restrict__ st) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -341,16 +404,22 @@ __global__ void forward_order1_kernel(const double* __restrict__ Qi, int M, doub
   const double a00 = q[0], a10 = q[ldq], a11 = q[ldq + 1];
   const double det = fma(a00, a11, -a10 * a10);
   if (!(a00 > 0.0) || !(det > 0.0) || !(det < INFINITY)) latch_failure(st, 1, a);
-  const double p = rsqrt_f64(det);
+  const double y = rsqrt_f64(det);
+  double p = y;
+  if constexpr (DISP) {
+    const double v0 = mi[2 * (size_t)a], v1 = mi[2 * (size_t)a + 1];
+    const double t = fma(a11 * v0, v0, fma(-2.0 * a10 * v0, v1, a00 * v1 * v1));
+    p *= exp(-0.5 * t * (y * y));
+  }
   const double m = (CONV == GBS_CLICK) ? 1.0 - p : fma(2.0, p, -1.0);
   if (m_out) m_out[a] = m;
   if (k_out) k_out[a] = m;
   if (p_out) p_out[a] = p;
 }
 
-template <int D, int CONV, bool WC, typename Idx, bool MX>
-static hipError_t launch_rec_t(int M, const double* Qi, const double* Qd, const double* pk,
-                               const float* E,
+template <int D, int CONV, bool WC, typename Idx, bool MX, bool DP>
+static hipError_t launch_rec_t(int M, const double* Qi, const double* Qd, const double* mi,
+                               const double* pk, const float* E,
                                const uint64_t* binom, const OrderTables& tab, double* m_out,
                                double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
   const uint64_t count = host_binom(M, D);
@@ -359,18 +428,20 @@ static hipError_t launch_rec_t(int M, const double* Qi, const double* Qd, const 
   const uint64_t grid = std::min<uint64_t>((count + block - 1) / block, kRecGrid);
   const size_t lds = (size_t)(D + 1) * (M + 1) * sizeof(Idx);
   if (lds <= 48 * 1024) {
-    hipLaunchKernelGGL((forward_rec_kernel<D, CONV, WC, true, Idx, MX>), dim3((unsigned)grid),
-                       dim3(block), lds, s, Qi, Qd, pk, E, M, count, binom, tab, m_out, k_out, p_out, st);
+    hipLaunchKernelGGL((forward_rec_kernel<D, CONV, WC, true, Idx, MX, DP>), dim3((unsigned)grid),
+                       dim3(block), lds, s, Qi, Qd, mi, pk, E, M, count, binom, tab, m_out, k_out,
+                       p_out, st);
   } else {
-    hipLaunchKernelGGL((forward_rec_kernel<D, CONV, WC, false, Idx, MX>), dim3((unsigned)grid),
-                       dim3(block), 0, s, Qi, Qd, pk, E, M, count, binom, tab, m_out, k_out, p_out, st);
+    hipLaunchKernelGGL((forward_rec_kernel<D, CONV, WC, false, Idx, MX, DP>), dim3((unsigned)grid),
+                       dim3(block), 0, s, Qi, Qd, mi, pk, E, M, count, binom, tab, m_out, k_out,
+                       p_out, st);
   }
   return hipGetLastError();
 }
 
-template <int D, int CONV, bool MX>
-static hipError_t launch_rec_w(int M, const double* Qi, const double* Qd, const double* pk,
-                               const float* E,
+template <int D, int CONV, bool MX, bool DP>
+static hipError_t launch_rec_w(int M, const double* Qi, const double* Qd, const double* mi,
+                               const double* pk, const float* E,
                                const uint64_t* binom, const OrderTables& tab, double* m_out,
                                double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
   // 32-bit rank and byte-offset arithmetic when every table of orders <= D
@@ -379,35 +450,52 @@ static hipError_t launch_rec_w(int M, const double* Qi, const double* Qd, const 
   for (int d = 1; d <= D; ++d) small = small && host_binom(M, d) < (1ull << 29);
   if (k_out) {
     if (small)
-      return launch_rec_t<D, CONV, true, uint32_t, MX>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
-    return launch_rec_t<D, CONV, true, uint64_t, MX>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+      return launch_rec_t<D, CONV, true, uint32_t, MX, DP>(M, Qi, Qd, mi, pk, E, binom, tab, m_out,
+                                                           k_out, p_out, st, s);
+    return launch_rec_t<D, CONV, true, uint64_t, MX, DP>(M, Qi, Qd, mi, pk, E, binom, tab, m_out,
+                                                         k_out, p_out, st, s);
   }
   if (small)
-    return launch_rec_t<D, CONV, false, uint32_t, MX>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
-  return launch_rec_t<D, CONV, false, uint64_t, MX>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+    return launch_rec_t<D, CONV, false, uint32_t, MX, DP>(M, Qi, Qd, mi, pk, E, binom, tab, m_out,
+                                                          k_out, p_out, st, s);
+  return launch_rec_t<D, CONV, false, uint64_t, MX, DP>(M, Qi, Qd, mi, pk, E, binom, tab, m_out,
+                                                        k_out, p_out, st, s);
+}
+
+template <int D, int CONV>
+static hipError_t launch_rec_v(int M, int flags, const double* Qi, const double* Qd,
+                               const double* mi, const double* pk, const float* E,
+                               const uint64_t* binom, const OrderTables& tab, double* m_out,
+                               double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
+  if (flags & GBS_MIXED)
+    return launch_rec_w<D, CONV, true, false>(M, Qi, Qd, mi, pk, E, binom, tab, m_out, k_out, p_out,
+                                              st, s);
+  if (mi)
+    return launch_rec_w<D, CONV, false, true>(M, Qi, Qd, mi, pk, E, binom, tab, m_out, k_out, p_out,
+                                              st, s);
+  return launch_rec_w<D, CONV, false, false>(M, Qi, Qd, mi, pk, E, binom, tab, m_out, k_out, p_out,
+                                             st, s);
 }
 
 template <int D>
 static hipError_t launch_rec_c(int M, int flags, const double* Qi, const double* Qd,
-                               const double* pk,
-                               const float* E, const uint64_t* binom, const OrderTables& tab,
-                               double* m_out, double* k_out, double* p_out, DeviceStatus* st,
-                               hipStream_t s) {
-  const bool mx = (flags & GBS_MIXED) != 0;
-  if (flags & GBS_PARITY) {
-    if (mx) return launch_rec_w<D, GBS_PARITY, true>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
-    return launch_rec_w<D, GBS_PARITY, false>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
-  }
-  if (mx) return launch_rec_w<D, GBS_CLICK, true>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
-  return launch_rec_w<D, GBS_CLICK, false>(M, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+                               const double* mi, const double* pk, const float* E,
+                               const uint64_t* binom, const OrderTables& tab, double* m_out,
+                               double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
+  if (flags & GBS_PARITY)
+    return launch_rec_v<D, GBS_PARITY>(M, flags, Qi, Qd, mi, pk, E, binom, tab, m_out, k_out,
+                                       p_out, st, s);
+  return launch_rec_v<D, GBS_CLICK>(M, flags, Qi, Qd, mi, pk, E, binom, tab, m_out, k_out, p_out,
+                                    st, s);
 }
 
 hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const double* Qd,
-                              const double* pk,
+                              const double* mi, const double* pk,
                               const float* E, const uint64_t* binom, const double* const* p_tab,
                               const double* const* m_tab, const double* const* k_tab,
                               double* m_out, double* k_out, double* p_out, DeviceStatus* st,
                               hipStream_t s) {
+  if (mi && (flags & GBS_MIXED)) return hipErrorInvalidValue;
   OrderTables tab{};
   for (int q = 1; q <= kMaxOrder; ++q) {
     tab.p[q] = p_tab[q];
@@ -417,23 +505,33 @@ hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const d
   if (d == 1) {
     const int block = 256;
     const int grid = (M + block - 1) / block;
-    if (flags & GBS_PARITY)
-      hipLaunchKernelGGL(forward_order1_kernel<GBS_PARITY>, dim3(grid), dim3(block), 0, s, Qi, M,
-                         m_out, k_out, p_out, st);
-    else
-      hipLaunchKernelGGL(forward_order1_kernel<GBS_CLICK>, dim3(grid), dim3(block), 0, s, Qi, M,
-                         m_out, k_out, p_out, st);
+    if (flags & GBS_PARITY) {
+      if (mi)
+        hipLaunchKernelGGL((forward_order1_kernel<GBS_PARITY, true>), dim3(grid), dim3(block), 0, s,
+                           Qi, mi, M, m_out, k_out, p_out, st);
+      else
+        hipLaunchKernelGGL((forward_order1_kernel<GBS_PARITY, false>), dim3(grid), dim3(block), 0,
+                           s, Qi, mi, M, m_out, k_out, p_out, st);
+    } else {
+      if (mi)
+        hipLaunchKernelGGL((forward_order1_kernel<GBS_CLICK, true>), dim3(grid), dim3(block), 0, s,
+                           Qi, mi, M, m_out, k_out, p_out, st);
+      else
+        hipLaunchKernelGGL((forward_order1_kernel<GBS_CLICK, false>), dim3(grid), dim3(block), 0, s,
+                           Qi, mi, M, m_out, k_out, p_out, st);
+    }
     return hipGetLastError();
   }
-  if (group_supported(d, M, flags))
+  // the tiled kernels take zero-mean states only
+  if (!mi && group_supported(d, M, flags))
     return launch_forward_group(d, M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
-  if (tile_supported(d, M, flags))
+  if (!mi && tile_supported(d, M, flags))
     return launch_forward_tile(d, M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
   switch (d) {
-    case 2: return launch_rec_c<2>(M, flags, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
-    case 3: return launch_rec_c<3>(M, flags, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
-    case 4: return launch_rec_c<4>(M, flags, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
-    case 5: return launch_rec_c<5>(M, flags, Qi, Qd, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+    case 2: return launch_rec_c<2>(M, flags, Qi, Qd, mi, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+    case 3: return launch_rec_c<3>(M, flags, Qi, Qd, mi, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+    case 4: return launch_rec_c<4>(M, flags, Qi, Qd, mi, pk, E, binom, tab, m_out, k_out, p_out, st, s);
+    case 5: return launch_rec_c<5>(M, flags, Qi, Qd, mi, pk, E, binom, tab, m_out, k_out, p_out, st, s);
     default: return hipErrorInvalidValue;
   }
 }

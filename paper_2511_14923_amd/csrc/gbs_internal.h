@@ -29,6 +29,9 @@ DeviceContext* current_context(hipError_t* err);
 // 2M x 2M FP64, built from sigma's lower triangle.
 hipError_t launch_build_q(const double* sigma, int M, double* Qi, hipStream_t s);
 
+// First moments in interleaved order (mi[2k] = mu[k], mi[2k+1] = mu[k+M]).
+hipError_t launch_build_mean(const double* mu, int M, double* mi, hipStream_t s);
+
 // Per-mode diagonal blocks of Q, 4 doubles per mode (x-x, p-x, p-p, 0).
 hipError_t launch_build_qdiag(const double* Qi, int M, double* Qd, hipStream_t s);
 
@@ -51,11 +54,13 @@ gbs_status finish_status(DeviceStatus* dev_status, int32_t flags, hipStream_t s)
 hipError_t launch_clear_status(DeviceStatus* st, hipStream_t s);
 
 // Order-d forward pass over all C(M, d) subsets.
-// FP64 reads Qi; MIXED reads pk and E.  corr and/or cum may be null (not
-// written); ptab (FP64 only, may be null) receives p(S) of every subset.
-hipError_t launch_forward(int d, int M, int flags, const double* Qi, const double* pk,
-                          const float* E, const uint64_t* binom, double* corr, double* cum,
-                          double* ptab, DeviceStatus* st, hipStream_t s);
+// FP64 reads Qi (and the interleaved first moments mi of a displaced state,
+// or null for zero mean); MIXED reads pk and E (zero mean only).  corr and/or
+// cum may be null (not written); ptab (FP64 only, may be null) receives p(S)
+// of every subset.
+hipError_t launch_forward(int d, int M, int flags, const double* Qi, const double* mi,
+                          const double* pk, const float* E, const uint64_t* binom, double* corr,
+                          double* cum, double* ptab, DeviceStatus* st, hipStream_t s);
 
 // Lower-order tables read by the order-recursive kernels: p[q], m[q], k[q]
 // point at the order-q blocks (q below the order being computed).
@@ -84,9 +89,10 @@ hipError_t launch_forward_group(int d, int M, int flags, const double* Qi, const
 // Order-recursive FP64 forward pass of order d (see gbs_forward_rec.hip):
 // p_tab/m_tab/k_tab[q] point at the order-q blocks of the lower-order tables
 // (q < d); m_out, k_out, p_out at the order-d blocks (each may be null).
-// GBS_MIXED reads pk and E (normalised Q) instead of Qi.
+// GBS_MIXED reads pk and E (normalised Q) instead of Qi.  mi (interleaved first
+// moments, FP64 only) selects the displaced-state kernels; null for zero mean.
 hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const double* Qd,
-                              const double* pk,
+                              const double* mi, const double* pk,
                               const float* E, const uint64_t* binom, const double* const* p_tab,
                               const double* const* m_tab, const double* const* k_tab,
                               double* m_out, double* k_out, double* p_out, DeviceStatus* st,

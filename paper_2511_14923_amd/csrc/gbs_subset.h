@@ -34,6 +34,47 @@ __device__ __forceinline__ void principal_minors(const Tri<2 * (D - K)>& A, doub
   }
 }
 
+// Displaced states: as principal_minors, also carrying the mean v over the
+// remaining blocks (reduced by every eliminated block, see pivot_mean) and the
+// quadratic form qT = mu_MASK^T Q_MASK^{-1} mu_MASK accumulated so far; writes
+// det(Q_T)^(-1/2) to p[T] and mu_T^T Q_T^{-1} mu_T to q[T].
+template <int D, int K, unsigned MASK>
+__device__ __forceinline__ void principal_minors_disp(const Tri<2 * (D - K)>& A,
+                                                      const double (&v)[2 * (D - K)], double pT,
+                                                      double qT, double (&p)[1 << D],
+                                                      double (&q)[1 << D], bool& bad) {
+  constexpr int n = 2 * (D - K);
+  const double a00 = A.a[0], a10 = A.a[1], a11 = A.a[2];
+  const double det = fma(a00, a11, -a10 * a10);
+  bad |= !(a00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
+  const double y = rsqrt_f64(det);
+  double vr[n > 2 ? n - 2 : 1];
+  const double qb = pivot_mean<n>(A, y * y, v, vr);
+  if constexpr (n == 2) {
+    p[MASK | (1u << K)] = pT * y;
+    q[MASK | (1u << K)] = qT + qb;
+    p[MASK] = pT;
+    q[MASK] = qT;
+  } else {
+    Tri<n - 2> S;
+    schur_leading_block<n>(A, y * y, S);
+    double vs[n - 2];
+#pragma unroll
+    for (int i = 0; i < n - 2; ++i) vs[i] = vr[i];
+    principal_minors_disp<D, K + 1, MASK | (1u << K)>(S, vs, pT * y, qT + qb, p, q, bad);
+    Tri<n - 2> R;
+#pragma unroll
+    for (int i = 2; i < n; ++i) {
+#pragma unroll
+      for (int j = 2; j <= i; ++j) R.a[tri(i - 2, j - 2)] = A.a[tri(i, j)];
+    }
+    double vk[n - 2];
+#pragma unroll
+    for (int i = 2; i < n; ++i) vk[i - 2] = v[i];
+    principal_minors_disp<D, K + 1, MASK>(R, vk, pT, qT, p, q, bad);
+  }
+}
+
 // m[B] for every B subset S from the vacuum probabilities (subset zeta transform).
 template <int D, int CONV>
 __device__ __forceinline__ void correlators_from_vacuum(const double (&p)[1 << D],
@@ -88,6 +129,29 @@ __device__ __forceinline__ void subset_fp64(const double* __restrict__ Qi, int M
   gather_q<D>(Qi, M, s, A);
   double p[1 << D];
   principal_minors<D, 0, 0u>(A, 1.0, p, bad);
+  pS = p[(1 << D) - 1];
+  double m[1 << D];
+  correlators_from_vacuum<D, CONV>(p, m);
+  corr = m[(1 << D) - 1];
+  if constexpr (WANT_CUM) cum = cumulant_from_correlators<D>(m);
+  else cum = 0.0;
+}
+
+// Displaced states (first moments in mi, interleaved): every vacuum
+// probability gains exp(-mu_T^T Q_T^{-1} mu_T / 2) (Eq. vacuum_gaussian_prob).
+template <int D, int CONV, bool WANT_CUM>
+__device__ __forceinline__ void subset_fp64_disp(const double* __restrict__ Qi,
+                                                 const double* __restrict__ mi, int M,
+                                                 const int (&s)[D], double& corr, double& cum,
+                                                 double& pS, bool& bad) {
+  Tri<2 * D> A;
+  gather_q<D>(Qi, M, s, A);
+  double v[2 * D];
+  gather_mean<D>(mi, s, v);
+  double p[1 << D], q[1 << D];
+  principal_minors_disp<D, 0, 0u>(A, v, 1.0, 0.0, p, q, bad);
+#pragma unroll
+  for (int T = 1; T < (1 << D); ++T) p[T] *= exp(-0.5 * q[T]);
   pS = p[(1 << D) - 1];
   double m[1 << D];
   correlators_from_vacuum<D, CONV>(p, m);

@@ -76,6 +76,15 @@ def test_invalid_arguments_rejected_on_host():
         P.GBS_E_INVALID_ARG, P.GBS_E_UNSUPPORTED)
     assert lib.gbs_cumulant_grad(10, fake, 3, 0, None, fake, None, None) == P.GBS_E_INVALID_ARG
     assert lib.gbs_cumulants_batched(0, None, 3, 0, None) == P.GBS_E_INVALID_ARG
+    # displaced states: mu required, FP64 only
+    assert lib.gbs_cumulants_displaced(10, fake, None, 3, 0, None, fake, None) == \
+        P.GBS_E_INVALID_ARG
+    assert lib.gbs_cumulants_displaced(10, fake, fake, 6, 0, None, fake, None) == \
+        P.GBS_E_INVALID_ARG
+    assert lib.gbs_cumulants_displaced(10, fake, fake, 3, 0, None, None, None) == \
+        P.GBS_E_INVALID_ARG
+    assert lib.gbs_cumulants_displaced(10, fake, fake, 3, P.GBS_MIXED, None, fake, None) == \
+        P.GBS_E_UNSUPPORTED
 
 
 def test_status_strings():
