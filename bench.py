@@ -119,14 +119,15 @@ def precision_errors(torch, P, corr64, cum64, corrmx, cummx):
     return out
 
 
-def fp64_parity_sample(np, O, G, inst, corr, cum, n=3000):
-    """Sampled FP64 outputs against the oracle: worst |delta| / tolerance."""
+def fp64_parity_sample(np, O, G, inst, corr, cum, n=3000, mu=None):
+    """Sampled FP64 outputs against the oracle (displaced when mu is given):
+    worst |delta| / tolerance."""
     worst = 0.0
     for d in range(1, K + 1):
         cnt = math.comb(M, d)
         ranks = G.random_ranks(cnt, min(n, cnt), seed=900 + d)
-        rc, rk = O.c_forward_sample(inst.sigma, d, ranks)
-        vmu, vkap = O.c_error_floor(inst.sigma, d, ranks)
+        rc, rk = O.c_forward_sample(inst.sigma, d, ranks, mu=mu)
+        vmu, vkap = O.c_error_floor(inst.sigma, d, ranks, mu=mu)
         off = O.order_offset(M, d)
         gc = corr[off + ranks]
         gk = cum[off + ranks]
@@ -290,7 +291,7 @@ def main():
             (P.GBS_ALL_MINORS if form.endswith("all_minors") else 0)
         res[form] = run_precision(P, torch, sigma, corr, cum, flags, args.steps, args.warmup, form,
                                   mu=mu if form == "displaced" else None)
-        if form in ("fp64", "mixed"):
+        if form in ("fp64", "mixed", "displaced"):
             bufs[form] = (corr, cum)
         else:
             del corr, cum
@@ -307,6 +308,12 @@ def main():
             del c64, k64
         if "fp64" in bufs and "mixed" in bufs:
             extra["mixed_error_vs_fp64"] = precision_errors(torch, P, *bufs["fp64"], *bufs["mixed"])
+        if "displaced" in bufs:
+            cd = bufs["displaced"][0].cpu().numpy()
+            kd = bufs["displaced"][1].cpu().numpy()
+            extra["displaced_worst_err_over_tol"] = fp64_parity_sample(
+                np, O, G, inst, cd, kd, mu=G.input_displacement(inst))
+            del cd, kd
     if not args.no_extras and not args.only:
         extra["extras"] = batched_and_adjoint(P, torch, G, 5)
     base = None

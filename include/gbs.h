@@ -148,9 +148,9 @@ GBS_API gbs_status gbs_cumulants(int32_t M, const double* sigma, int32_t max_ord
  *   mu     device, 2M FP64 first moments, xxpp order (index k is <x_k>, k+M is <p_k>)
  *   flags  GBS_CLICK/GBS_PARITY | GBS_ASYNC | GBS_TIMING | GBS_ALL_MINORS;
  *          GBS_MIXED gives GBS_E_UNSUPPORTED (FP64 only)
- * Other arguments, layouts, ownership and errors as gbs_cumulants.  The
- * default kernels are the order-recursive ones (one factorisation and one
- * triangular solve of the mean per subset, lower orders read from tables). */
+ * Other arguments, layouts, ownership and errors as gbs_cumulants; the same
+ * kernels run, each also carrying the mean through its factorisation (one
+ * forward substitution of mu per factor). */
 GBS_API gbs_status gbs_cumulants_displaced(int32_t M, const double* sigma, const double* mu,
                                    int32_t max_order, int32_t flags, double* corr, double* cum,
                                    void* stream);

@@ -22,7 +22,17 @@
 // cumulants (Eq. cumulant_corr_main grouped by the block containing e; App. B,
 // Eq. correlators_expanded_2).
 //
-// A tile is a run of consecutive B's (at most kGroupB) whose groups need at
+// Displaced states (first moments mu, Eq. vacuum_gaussian_prob): the same
+// factorisation also gives z = L^{-1} mu in the order [P, b_0, e] (z_P and
+// z_e(T) once per group, z_{b_0} and z_e(B) once per B), and for a leading set
+// U of the order the quadratic form splits as
+//   mu_{U+a}^T Q_{U+a}^{-1} mu_{U+a} = |z_U|^2 + r^T (Q_aa - y_U^T y_U)^{-1} r,
+//   r = mu_a - y_U^T z_U,
+// so every probability computed here gains exp(-q/2) from two more 2-vectors
+// per block row; |z|^2 of the T, B' and B parts is folded into the per-group
+// and per-B probabilities.
+//
+// A tile is a run of consecutive B's (at most GL::kB) whose groups need at
 // most rmax (T, a) records; the host plans the tiles once per (M, d).  Per
 // tile: phase 1 builds the per-B records (lane = B, one part per wave) and the
 // group list; phase 1b builds the (T, a) records (one per thread); phase 2
@@ -46,8 +56,11 @@ constexpr int kGroupG = 16;         // groups per tile at most
 constexpr int kGroupThreads = 256;  // threads per workgroup (4 waves)
 constexpr int kGroupRmax = 148;     // (T, a) records per tile at most (M - d + 1 needed)
 
-template <int NB>
+template <int NB, bool DISP>
 struct GroupLayout {
+  // B's per tile: fewer for displaced states, whose larger records must still
+  // let three workgroups share a compute unit's LDS
+  static constexpr int kB = DISP ? 36 : kGroupB;
   static constexpr int NPm = NB - 2;       // |P|
   static constexpr int NT = NB - 1;        // |T|
   static constexpr int NTS = 1 << NT;      // subsets of T
@@ -61,12 +74,13 @@ struct GroupLayout {
   static constexpr int nLb = 4 * NPm + 3;
   static constexpr int dLe = dLb + nLb;         // e rows against b_0 ([r][2]), then the e block
   static constexpr int nLe = 7;
-  static constexpr int dP = dLe + nLe;          // p(B'), p(B)
+  static constexpr int dP = dLe + nLe;          // p(B'), p(B) (displaced: with exp(-|z|^2 / 2))
   static constexpr int dMB = dP + 2;            // m(B)
   static constexpr int dMW = dMB + 1;           // m(W), W = 1 .. FULLP (index W - 1)
   static constexpr int dKB = dMW + (NP - 1);    // k(R + e), R = 0 .. FULLP
   static constexpr int dME = dKB + NP;          // m(R + e), R = 0 .. FULLP
-  static constexpr int nD = dME + NP;
+  static constexpr int dZ = dME + NP;           // displaced: z_{b_0} [2], z_e(B) [2]
+  static constexpr int nD = dZ + (DISP ? 4 : 0);
   static constexpr int nDpad = (nD + 1) & ~1;
   // per-B record, 32-bit words
   static constexpr int wStart = 0;              // first rank of the B-block, tile relative
@@ -74,7 +88,8 @@ struct GroupLayout {
   static constexpr int wRbase = 2;              // (T, a) record of a = 0 for this B's group
   static constexpr int wOP = 3;                 // rank parts (less start) of p({a} + U), b_0 in U
   static constexpr int nOP = NP - 2;            // all U containing b_0 except B' and B
-  static constexpr int nW = wOP + nOP;
+  static constexpr int wG = wOP + nOP;          // this B's group (displaced states)
+  static constexpr int nW = wG + (DISP ? 1 : 0);
   static constexpr int nWpad = (nW + 3) & ~3;
   static constexpr int bytes = nDpad * 8 + nWpad * 4;
   // (T, a) record, doubles; stored as 16-byte units, unit q of record i at
@@ -93,9 +108,10 @@ struct GroupLayout {
   static constexpr int gE = gP + tri_size(I0);  // e rows against P: [r][k < I0]
   static constexpr int gS = gE + 2 * I0;        // Q_ee - L_eP L_eP^T: s00, s10, s11
   static constexpr int gEd = gS + 3;            // e block of Q_T: 1/L, L, 1/L
-  static constexpr int gpP = gEd + 3;           // p(P)
-  static constexpr int gpT = gpP + 1;           // p(T)
-  static constexpr int gN = ((gpT + 1) + 1) & ~1;
+  static constexpr int gpP = gEd + 3;           // p(P) (displaced: with exp(-|z_P|^2 / 2))
+  static constexpr int gpT = gpP + 1;           // p(T) (displaced: with exp(-|z_T|^2 / 2))
+  static constexpr int gZ = gpT + 1;            // displaced: z_P [2|P|], z_e(T) [2]
+  static constexpr int gN = ((gZ + (DISP ? I0 + 2 : 0)) + 1) & ~1;
   static constexpr int gbytes = gN * 8;
 };
 
@@ -116,15 +132,16 @@ __host__ __device__ constexpr bool t_leading(int t) {
 
 }  // namespace
 
-template <int D, int CONV, bool WANT_CUM>
+template <int D, int CONV, bool WANT_CUM, bool DISP>
 __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
-    const double* __restrict__ Qi, const double* __restrict__ Qd, int M,
+    const double* __restrict__ Qi, const double* __restrict__ Qd,
+    const double* __restrict__ mi, int M,
     const uint64_t* __restrict__ plan, uint32_t ntiles, const uint64_t* __restrict__ binom,
     OrderTables tab, double* __restrict__ m_out, double* __restrict__ k_out,
     double* __restrict__ p_out, DeviceStatus* __restrict__ st, int nwin_max) {
   constexpr int rmax = kGroupRmax;
   constexpr int NB = D - 1;
-  using GL = GroupLayout<NB>;
+  using GL = GroupLayout<NB, DISP>;
   constexpr int NPm = GL::NPm;
   constexpr int NT = GL::NT;
   constexpr int NTS = GL::NTS;
@@ -137,7 +154,7 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
   extern __shared__ __align__(16) unsigned char smem[];
   // [B records][(T, a) records][group records][binomials][bitmap][first run per window]
   unsigned char* brec = smem;
-  unsigned char* rrec = smem + kGroupB * GL::bytes;
+  unsigned char* rrec = smem + GL::kB * GL::bytes;
   double* grec = reinterpret_cast<double*>(rrec + (size_t)rmax * GL::rbytes);
   uint32_t* bin = reinterpret_cast<uint32_t*>(grec + kGroupG * GL::gN);
   const int ld = M + 1;
@@ -274,8 +291,26 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
           gr[GL::gEd + 0] = dinv[I0];
           gr[GL::gEd + 1] = A.a[tri(I0 + 1, I0)];
           gr[GL::gEd + 2] = dinv[I0 + 1];
-          gr[GL::gpP] = pP;
-          gr[GL::gpT] = pP * dinv[I0] * dinv[I0 + 1];
+          double eP = 1.0, eT = 1.0;
+          if constexpr (DISP) {
+            // z_T = L_T^{-1} mu_T (order P, e); |z_P|^2 and |z_T|^2
+            double z[NTT];
+            double qP = 0.0, qT = 0.0;
+#pragma unroll
+            for (int i = 0; i < NTT; ++i) {
+              double v = mi[2 * tm[i >> 1] + (i & 1)];
+#pragma unroll
+              for (int k = 0; k < i; ++k) v = fma(-A.a[tri(i, k)], z[k], v);
+              z[i] = v * dinv[i];
+              gr[GL::gZ + i] = z[i];
+              if (i < I0) qP = fma(z[i], z[i], qP);
+              qT = fma(z[i], z[i], qT);
+            }
+            eP = exp(-0.5 * qP);
+            eT = exp(-0.5 * qT);
+          }
+          gr[GL::gpP] = pP * eP;
+          gr[GL::gpT] = pP * dinv[I0] * dinv[I0 + 1] * eT;
         }
       } else if (wave == 1) {
         if (nonempty) {
@@ -322,6 +357,7 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
           rw[GL::wStart] = start;
           rw[GL::wRow] = 2u * (uint32_t)b[0] * ldq8;
           rw[GL::wRbase] = gbase;
+          if constexpr (DISP) rw[GL::wG] = (uint32_t)g;
 #pragma unroll
           for (int u = 1; u < FULL; u += 2) {
             if (u == FULLP) continue;
@@ -457,9 +493,38 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
         rd[GL::dLe + 4] = iex;
         rd[GL::dLe + 5] = lpx;
         rd[GL::dLe + 6] = iep;
-        const double pBp = gr[GL::gpP] * ib0 * ib1;
+        double eb = 1.0, ee = 1.0;
+        if constexpr (DISP) {
+          // z_{b_0} and z_e(B): the b_0 and e rows of L_B^{-1} mu_B (order P, b_0, e)
+          double zb[2], ze[2];
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            double v = mi[2 * b0 + r];
+#pragma unroll
+            for (int k = 0; k < I0; ++k) v = fma(-lb[r][k], gr[GL::gZ + k], v);
+            if (r == 1) v = fma(-l10, zb[0], v);
+            zb[r] = v * (r ? ib1 : ib0);
+          }
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            double v = mi[2 * e + r];
+#pragma unroll
+            for (int k = 0; k < I0; ++k) v = fma(-gr[GL::gE + r * I0 + k], gr[GL::gZ + k], v);
+            v = fma(-le[r][0], zb[0], v);
+            v = fma(-le[r][1], zb[1], v);
+            if (r == 1) v = fma(-lpx, ze[0], v);
+            ze[r] = v * (r ? iep : iex);
+          }
+          rd[GL::dZ + 0] = zb[0];
+          rd[GL::dZ + 1] = zb[1];
+          rd[GL::dZ + 2] = ze[0];
+          rd[GL::dZ + 3] = ze[1];
+          eb = exp(-0.5 * fma(zb[0], zb[0], zb[1] * zb[1]));
+          ee = exp(-0.5 * fma(ze[0], ze[0], ze[1] * ze[1]));
+        }
+        const double pBp = gr[GL::gpP] * ib0 * ib1 * eb;
         rd[GL::dP] = pBp;
-        rd[GL::dP + 1] = pBp * iex * iep;
+        rd[GL::dP + 1] = pBp * iex * iep * ee;
       }
     } else {
       const uint32_t nrec = s_nrec;
@@ -485,10 +550,24 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
         double s00 = qd0.x, s10 = qd0.y, s11 = qd2;
         double pt[NTS];
         bool bad = false;
+        // displaced: r = mu_a - y_U^T z_U and |z_U|^2 along the leading sets U
+        double r0 = 0.0, r1 = 0.0, qz = 0.0;
+        if constexpr (DISP) {
+          const double2 m = *reinterpret_cast<const double2*>(mi + 2 * (size_t)a);
+          r0 = m.x;
+          r1 = m.y;
+        }
+        // exp(-(|z_U|^2 + r^T S^{-1} r) / 2) with y = det(S)^(-1/2)
+        auto mean_factor = [&](double y) -> double {
+          if constexpr (!DISP) return 1.0;
+          const double t = fma(s11 * r0, r0, fma(-2.0 * s10 * r0, r1, s00 * r1 * r1));
+          return exp(-0.5 * fma(t, y * y, qz));
+        };
         {
           const double det = fma(s00, s11, -s10 * s10);
           bad |= !(s00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
-          pt[0] = rsqrt_f64(det);
+          const double y = rsqrt_f64(det);
+          pt[0] = y * mean_factor(y);
         }
         double y0[I0 > 0 ? I0 : 1], y1[I0 > 0 ? I0 : 1];
         double pl = 1.0;
@@ -509,10 +588,17 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
           s10 = fma(-y0[i], y1[i], s10);
           s11 = fma(-y1[i], y1[i], s11);
           pl *= di;
+          if constexpr (DISP) {
+            const double z = gr[GL::gZ + i];
+            r0 = fma(-y0[i], z, r0);
+            r1 = fma(-y1[i], z, r1);
+            qz = fma(z, z, qz);
+          }
           if (i & 1) {
             const double det = fma(s00, s11, -s10 * s10);
             bad |= !(s00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
-            pt[(2 << (i >> 1)) - 1] = pl * rsqrt_f64(det);
+            const double y = rsqrt_f64(det);
+            pt[(2 << (i >> 1)) - 1] = pl * y * mean_factor(y);
           }
         }
 #pragma unroll
@@ -545,9 +631,17 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
           s00 = fma(-ep0, ep0, s00);
           s10 = fma(-ep0, ep1, s10);
           s11 = fma(-ep1, ep1, s11);
+          if constexpr (DISP) {
+            // |z_T|^2 is already in p(T); only the a block's share remains
+            const double zx = gr[GL::gZ + I0], zp = gr[GL::gZ + I0 + 1];
+            r0 = fma(-ex0, zx, fma(-ep0, zp, r0));
+            r1 = fma(-ex1, zx, fma(-ep1, zp, r1));
+            qz = 0.0;
+          }
           const double det = fma(s00, s11, -s10 * s10);
           bad |= !(s00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
-          pt[NTS - 1] = gr[GL::gpT] * rsqrt_f64(det);
+          const double y = rsqrt_f64(det);
+          pt[NTS - 1] = gr[GL::gpT] * y * mean_factor(y);
         }
         if (bad) {  // {a} + T is an order d-1 subset with a non-positive pivot
           uint32_t rk = a;
@@ -602,6 +696,26 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
       double s00 = sPa.x, s10 = sPa.y, s11 = ru[(GL::rS / 2 + 1) * rmax].x;
       double yb0[2], yb1[2];
       bool bad = false;
+      // displaced: r = mu_a - y^T z over the rows eliminated so far (|z|^2 of
+      // B' and B is already in p(B') and p(B))
+      double r0 = 0.0, r1 = 0.0;
+      if constexpr (DISP) {
+        const double* gz = grec + rw[GL::wG] * GL::gN + GL::gZ;
+        const double2 m = *reinterpret_cast<const double2*>(mi + 2 * (size_t)a);
+        r0 = m.x;
+        r1 = m.y;
+#pragma unroll
+        for (int k = 0; k < I0; ++k) {
+          const double2 yk = ru[(GL::rY / 2 + k) * rmax];
+          r0 = fma(-yk.x, gz[k], r0);
+          r1 = fma(-yk.y, gz[k], r1);
+        }
+      }
+      auto mean_factor = [&](double y) -> double {  // exp(-r^T S^{-1} r / 2), y = det(S)^(-1/2)
+        if constexpr (!DISP) return 1.0;
+        const double t = fma(s11 * r0, r0, fma(-2.0 * s10 * r0, r1, s00 * r1 * r1));
+        return exp(-0.5 * t * (y * y));
+      };
 #pragma unroll
       for (int rrow = 0; rrow < 2; ++rrow) {
         double v0 = rrow ? qb1.x : qb0.x, v1 = rrow ? qb1.y : qb0.y;
@@ -625,10 +739,19 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
         s11 = fma(-yb1[rrow], yb1[rrow], s11);
       }
       double pA, pS;
+      if constexpr (DISP) {
+#pragma unroll
+        for (int rrow = 0; rrow < 2; ++rrow) {
+          const double z = rd[GL::dZ + rrow];
+          r0 = fma(-yb0[rrow], z, r0);
+          r1 = fma(-yb1[rrow], z, r1);
+        }
+      }
       {
         const double det = fma(s00, s11, -s10 * s10);
         bad |= !(s00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
-        pA = rd[GL::dP] * rsqrt_f64(det);
+        const double y = rsqrt_f64(det);
+        pA = rd[GL::dP] * y * mean_factor(y);
       }
       double ye0[2], ye1[2];
 #pragma unroll
@@ -650,10 +773,19 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
         s10 = fma(-ye0[rrow], ye1[rrow], s10);
         s11 = fma(-ye1[rrow], ye1[rrow], s11);
       }
+      if constexpr (DISP) {
+#pragma unroll
+        for (int rrow = 0; rrow < 2; ++rrow) {
+          const double z = rd[GL::dZ + 2 + rrow];
+          r0 = fma(-ye0[rrow], z, r0);
+          r1 = fma(-ye1[rrow], z, r1);
+        }
+      }
       {
         const double det = fma(s00, s11, -s10 * s10);
         bad |= !(s00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
-        pS = rd[GL::dP + 1] * rsqrt_f64(det);
+        const double y = rsqrt_f64(det);
+        pS = rd[GL::dP + 1] * y * mean_factor(y);
       }
       if (bad) latch_failure(st, D, (int64_t)r);
 #pragma unroll
@@ -732,10 +864,10 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
 namespace {
 
 // Tiles of consecutive B's (colex order of the (d-1)-subsets) such that each
-// holds at most kGroupB B's of at most kGroupG groups, which need at most rmax
+// holds at most kB B's of at most kGroupG groups, which need at most rmax
 // (T, a) records.  A group is all B = {b_0} + T with b_0 < min T; within a tile
 // it needs the records a < (largest b_0 of the group in the tile).
-std::vector<uint64_t> plan_tiles(int M, int NB, int rmax) {
+std::vector<uint64_t> plan_tiles(int M, int NB, int rmax, int kB) {
   std::vector<uint64_t> tiles;
   uint32_t beta = 0, tstart = 0;
   int nB = 0, rec = 0, ng = 0;
@@ -754,11 +886,11 @@ std::vector<uint64_t> plan_tiles(int M, int NB, int rmax) {
     const int gsize = t[0];  // b_0 = 0 .. t_0 - 1
     int k = 0;
     while (k < gsize) {
-      int n = std::min(gsize - k, kGroupB - nB);
+      int n = std::min(gsize - k, kB - nB);
       int need = k + n - 1;  // records a < max b_0 = k + n - 1
       if (rec + need > rmax || ng == kGroupG) {
         close();
-        n = std::min(gsize - k, kGroupB);
+        n = std::min(gsize - k, kB);
         need = k + n - 1;
       }
       nB += n;
@@ -766,7 +898,7 @@ std::vector<uint64_t> plan_tiles(int M, int NB, int rmax) {
       ++ng;
       beta += (uint32_t)n;
       k += n;
-      if (nB == kGroupB) close();
+      if (nB == kB) close();
     }
     // next T in colex order
     int i = 0;
@@ -780,9 +912,9 @@ std::vector<uint64_t> plan_tiles(int M, int NB, int rmax) {
 }
 
 struct PlanKey {
-  int device, M, NB;
+  int device, M, NB, kB;
   bool operator<(const PlanKey& o) const {
-    return std::tie(device, M, NB) < std::tie(o.device, o.M, o.NB);
+    return std::tie(device, M, NB, kB) < std::tie(o.device, o.M, o.NB, o.kB);
   }
 };
 struct Plan {
@@ -794,17 +926,17 @@ std::map<PlanKey, Plan> g_plans;
 
 int group_rmax(int M, int NB) { return M - NB <= kGroupRmax ? M - NB : -1; }
 
-hipError_t get_plan(int M, int NB, Plan* out) {
+hipError_t get_plan(int M, int NB, int kB, Plan* out) {
   int device = 0;
   hipError_t e = hipGetDevice(&device);
   if (e != hipSuccess) return e;
   std::lock_guard<std::mutex> lock(g_plan_mu);
-  auto it = g_plans.find(PlanKey{device, M, NB});
+  auto it = g_plans.find(PlanKey{device, M, NB, kB});
   if (it != g_plans.end()) {
     *out = it->second;
     return hipSuccess;
   }
-  const std::vector<uint64_t> tiles = plan_tiles(M, NB, group_rmax(M, NB));
+  const std::vector<uint64_t> tiles = plan_tiles(M, NB, group_rmax(M, NB), kB);
   Plan p;
   p.ntiles = (uint32_t)tiles.size();
   if (!tiles.empty()) {
@@ -816,74 +948,101 @@ hipError_t get_plan(int M, int NB, Plan* out) {
       return e;
     }
   }
-  g_plans[PlanKey{device, M, NB}] = p;
+  g_plans[PlanKey{device, M, NB, kB}] = p;
   *out = p;
   return hipSuccess;
 }
 
-template <int NB>
+template <int NB, bool DISP>
+int group_windows(int M) {
+  return (GroupLayout<NB, DISP>::kB * (M - NB) + 63) / 64 + 1;
+}
+
+template <int NB, bool DISP>
 size_t group_lds(int M) {
+  using GL = GroupLayout<NB, DISP>;
   const int D = NB + 1;
-  const int nwin = (kGroupB * (M - NB) + 63) / 64 + 1;
-  return (size_t)kGroupB * GroupLayout<NB>::bytes +
-         (size_t)kGroupRmax * GroupLayout<NB>::rbytes + (size_t)kGroupG * GroupLayout<NB>::gbytes +
+  return (size_t)GL::kB * GL::bytes + (size_t)kGroupRmax * GL::rbytes +
+         (size_t)kGroupG * GL::gbytes +
          (size_t)(((D + 1) * (M + 1) + 1) & ~1) * sizeof(uint32_t) +
-         (size_t)nwin * (sizeof(uint64_t) + 1);
+         (size_t)group_windows<NB, DISP>(M) * (sizeof(uint64_t) + 1);
+}
+
+template <bool DISP>
+size_t group_lds_d(int d, int M) {
+  switch (d) {
+    case 3: return group_lds<2, DISP>(M);
+    case 4: return group_lds<3, DISP>(M);
+    default: return group_lds<4, DISP>(M);
+  }
 }
 
 }  // namespace
 
-bool group_supported(int d, int M, int flags) {
+bool group_supported(int d, int M, int flags, bool displaced) {
   if (d < 3 || d > kMaxOrder || (flags & GBS_MIXED)) return false;
   for (int q = 1; q <= d; ++q)
     if (host_binom(M, q) >= (1ull << 29)) return false;
   if (group_rmax(M, d - 1) < 0) return false;
-  size_t lds = 0;
-  switch (d) {
-    case 3: lds = group_lds<2>(M); break;
-    case 4: lds = group_lds<3>(M); break;
-    default: lds = group_lds<4>(M); break;
-  }
+  const size_t lds = displaced ? group_lds_d<true>(d, M) : group_lds_d<false>(d, M);
   return lds <= 64 * 1024;
 }
 
-template <int D, int CONV, bool WC>
-static hipError_t launch_group_t(int M, const double* Qi, const double* Qd, const uint64_t* binom,
-                                 const OrderTables& tab, double* m_out, double* k_out,
-                                 double* p_out, DeviceStatus* st, hipStream_t s) {
+template <int D, int CONV, bool WC, bool DISP>
+static hipError_t launch_group_t(int M, const double* Qi, const double* Qd, const double* mi,
+                                 const uint64_t* binom, const OrderTables& tab, double* m_out,
+                                 double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
   constexpr int NB = D - 1;
   if (host_binom(M, D) == 0) return hipSuccess;
   Plan plan;
-  hipError_t e = get_plan(M, NB, &plan);
+  hipError_t e = get_plan(M, NB, GroupLayout<NB, DISP>::kB, &plan);
   if (e != hipSuccess) return e;
   if (plan.ntiles == 0) return hipSuccess;
-  const int nwin = (kGroupB * (M - NB) + 63) / 64 + 1;
-  const size_t lds = group_lds<NB>(M);
-  hipLaunchKernelGGL((forward_group_kernel<D, CONV, WC>), dim3(plan.ntiles), dim3(kGroupThreads),
-                     lds, s, Qi, Qd, M, plan.dev, plan.ntiles, binom, tab, m_out, k_out, p_out, st,
-                     nwin);
+  const int nwin = group_windows<NB, DISP>(M);
+  const size_t lds = group_lds<NB, DISP>(M);
+  hipLaunchKernelGGL((forward_group_kernel<D, CONV, WC, DISP>), dim3(plan.ntiles),
+                     dim3(kGroupThreads), lds, s, Qi, Qd, mi, M, plan.dev, plan.ntiles, binom, tab,
+                     m_out, k_out, p_out, st, nwin);
   return hipGetLastError();
+}
+
+template <int D, int CONV, bool DISP>
+static hipError_t launch_group_w(int M, const double* Qi, const double* Qd, const double* mi,
+                                 const uint64_t* binom, const OrderTables& tab, double* m_out,
+                                 double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
+  if (k_out)
+    return launch_group_t<D, CONV, true, DISP>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st,
+                                               s);
+  return launch_group_t<D, CONV, false, DISP>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st,
+                                              s);
 }
 
 template <int D>
 static hipError_t launch_group_c(int M, int flags, const double* Qi, const double* Qd,
-                                 const uint64_t* binom, const OrderTables& tab, double* m_out,
-                                 double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
+                                 const double* mi, const uint64_t* binom, const OrderTables& tab,
+                                 double* m_out, double* k_out, double* p_out, DeviceStatus* st,
+                                 hipStream_t s) {
   if (flags & GBS_PARITY) {
-    if (k_out) return launch_group_t<D, GBS_PARITY, true>(M, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
-    return launch_group_t<D, GBS_PARITY, false>(M, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
+    if (mi)
+      return launch_group_w<D, GBS_PARITY, true>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out,
+                                                 st, s);
+    return launch_group_w<D, GBS_PARITY, false>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out,
+                                                st, s);
   }
-  if (k_out) return launch_group_t<D, GBS_CLICK, true>(M, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
-  return launch_group_t<D, GBS_CLICK, false>(M, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
+  if (mi)
+    return launch_group_w<D, GBS_CLICK, true>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st,
+                                              s);
+  return launch_group_w<D, GBS_CLICK, false>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s);
 }
 
 hipError_t launch_forward_group(int d, int M, int flags, const double* Qi, const double* Qd,
-                                const uint64_t* binom, const OrderTables& tab, double* m_out,
-                                double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
+                                const double* mi, const uint64_t* binom, const OrderTables& tab,
+                                double* m_out, double* k_out, double* p_out, DeviceStatus* st,
+                                hipStream_t s) {
   switch (d) {
-    case 3: return launch_group_c<3>(M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
-    case 4: return launch_group_c<4>(M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
-    case 5: return launch_group_c<5>(M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
+    case 3: return launch_group_c<3>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s);
+    case 4: return launch_group_c<4>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s);
+    case 5: return launch_group_c<5>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -79,12 +79,14 @@ hipError_t launch_forward_tile(int d, int M, int flags, const double* Qi, const 
 
 // Group-tiled FP64 kernel of order d (3..5), the default where it applies:
 // 32-bit ranks and LDS for (M - d + 1) records per tile; see
-// gbs_forward_group.hip.  Tile plans are built on the host once per (M, d)
-// and kept on the device until the process ends.
-bool group_supported(int d, int M, int flags);
+// gbs_forward_group.hip.  Tile plans are built on the host once per (M, d,
+// tile width) and kept on the device until the process ends.  mi: interleaved
+// first moments of a displaced state, or null.
+bool group_supported(int d, int M, int flags, bool displaced);
 hipError_t launch_forward_group(int d, int M, int flags, const double* Qi, const double* Qd,
-                                const uint64_t* binom, const OrderTables& tab, double* m_out,
-                                double* k_out, double* p_out, DeviceStatus* st, hipStream_t s);
+                                const double* mi, const uint64_t* binom, const OrderTables& tab,
+                                double* m_out, double* k_out, double* p_out, DeviceStatus* st,
+                                hipStream_t s);
 
 // Order-recursive FP64 forward pass of order d (see gbs_forward_rec.hip):
 // p_tab/m_tab/k_tab[q] point at the order-q blocks of the lower-order tables

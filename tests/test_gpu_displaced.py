@@ -112,6 +112,15 @@ def test_displaced_m144_k5_sampled(P, conv):
     _check_sampled(P, inst.sigma, mu, 5, picks, conv, "M=144")
 
 
+def test_displaced_beyond_group_kernel(P):
+    """M = 160, K = 4: orders 3 and 4 need more (T, a) records than the group
+    kernel holds, so displaced calls take the order-recursive kernel there."""
+    _say("case: displaced M=160 K=4 sampled")
+    inst = G.make_instance("m144_k5", M=160, seed=45)
+    mu = G.input_displacement(inst, seed=46)
+    _check_sampled(P, inst.sigma, mu, 4, _picks(160, 4, 4000, 70, tail=300), 0, "M=160")
+
+
 def test_displaced_64bit_ranks(P):
     """M = 1500, K = 3: more than 2^29 order-3 subsets (64-bit rank arithmetic)."""
     _say("case: displaced M=1500 K=3 sampled")
