@@ -7,11 +7,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "gbs_oracle.c")
+    srcs = [os.path.join(HERE, "gbs_oracle.c"), os.path.join(HERE, "gbs_sampler_oracle.c")]
     out = os.path.join(HERE, "liboracle.so")
     tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-result",
-           "-o", tmp, src, "-lm"]
+           "-o", tmp] + srcs + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
