@@ -196,6 +196,70 @@ def batched_and_adjoint(P, torch, G, steps):
     return out
 
 
+def sampler_terms(M_, K_):
+    """Expansion terms one sample evaluates (the sums of Eqs. methprob, b, a for
+    K = 3; Eqs. probade, probpartialade, probelidedade, probdoubleelidedade for
+    K = 5), each one product with one per-sample table value."""
+    def c(a, b):
+        return math.comb(a, b) if a >= 0 else 0
+    tot = 0
+    for n in range(1, M_ + 1):
+        if K_ == 3:
+            tot += 1 + (n - 1) + c(n - 1, 2)                              # p
+            tot += (n - 1) * (n - 1)                                      # p1
+            tot += sum(1 + (n - l) for l in range(1, n + 1))              # p+
+        else:
+            tot += 1 + (n - 1) + c(n - 1, 2) + c(n - 1, 3) + c(n - 1, 4)  # p
+            tot += sum(1 + (n - l) + c(n - l, 2) for l in range(1, n + 1))  # p+
+            tot += (n - 1) * (1 + (n - 2) + c(n - 2, 2))                  # p1
+            tot += c(n - 1, 2) * (n - 2)                                  # p2
+    return tot
+
+
+def sampler_legs(P, torch, np, G, sigma, counts):
+    """Stage 2 on the stage-1 output: parity cumulants of the M = 144 workload
+    (gbs_cumulants, GBS_PARITY) -> gbs_sample, single elision (K = 3) and
+    double elision (K = 5); uniforms from a seeded device generator."""
+    out = {}
+    for K_, n in counts:
+        _, kap = P.gbs_cumulants(M, sigma, K_, P.GBS_PARITY, want_corr=False)
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(2511 + K_)
+        u = torch.rand((M, n), dtype=torch.float64, device="cuda:0", generator=g)
+        if K_ == 3:  # warm-up: one workgroup (a K = 5 workgroup alone runs for seconds)
+            P.gbs_sample(M, kap, K_, u[:, :64].contiguous())
+        torch.cuda.synchronize()
+        log(f"[bench] sampler K={K_}: {n} samples")
+        t0 = time.perf_counter()
+        bits, prob, _ = P.gbs_sample(M, kap, K_, u, flags=P.GBS_TIMING)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms = sum(ms for st, _, ms in P.gbs_last_timings() if st == "sample")
+        terms = sampler_terms(M, K_) * n
+        out[f"sample_k{K_}_m144"] = {
+            "samples": n, "seconds": wall, "samples_per_s": n / wall, "kernel_ms": kms,
+            "terms_per_sample": sampler_terms(M, K_), "terms_per_s": terms / (kms * 1e-3),
+            "table_read_gb_per_s": 8.0 * terms / (kms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": 8.0 * terms / (kms * 1e-3) / 8e12,
+            "mean_clicks": float(bits.float().mean().item() * M),
+            "method": "single elision" if K_ == 3 else "double elision"}
+        del kap, u, bits, prob
+    # the C oracle on the host cores, same sizes, seeded synthetic cumulants
+    import oracle as O
+    from oracle import sampler as S
+    for K_, n in ((3, 512), (5, 16)):
+        cum = G.synthetic_parity_cumulants(M, K_, 7)
+        uu = G.sampler_uniforms(M, n, 8)
+        t0 = time.perf_counter()
+        S.c_sample(cum, M, K_, u=uu)
+        dt = time.perf_counter() - t0
+        out[f"sample_k{K_}_m144"]["cpu_oracle"] = {
+            "samples": n, "seconds": dt, "samples_per_s": n / dt, "cores": O.c_threads(0),
+            "kind": "oracle"}
+        log(f"[bench] sampler K={K_} cpu oracle: {n} samples in {dt:.1f} s")
+    return out
+
+
 def cpu_baseline(np, O, G, inst, seconds):
     """The C oracle on the host cores over a random sample of the workload's
     subsets (all orders, in proportion to their counts)."""
@@ -233,7 +297,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="which form gives the headline value (both are measured)")
     ap.add_argument("--only", choices=["fp64", "mixed", "fp64_all_minors", "mixed_all_minors",
-                                       "displaced"],
+                                       "displaced", "sampler"],
                     default=None, help="measure one form only (profiling runs)")
     ap.add_argument("--all-minors", action="store_true",
                     help="also measure the all-minors kernel (GBS_ALL_MINORS) of both precisions")
@@ -242,6 +306,9 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint measurements")
+    ap.add_argument("--no-sampler", action="store_true", help="skip the stage-2 sampler legs")
+    ap.add_argument("--samples-k3", type=int, default=262144)
+    ap.add_argument("--samples-k5", type=int, default=16384)
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -274,7 +341,9 @@ def main():
     N = P.gbs_total_outputs(M, K)
     log(f"[bench] M={M} K={K} outputs={N}")
 
-    forms = [args.only] if args.only else ["fp64", "mixed"]
+    forms = [args.only] if args.only and args.only != "sampler" else ["fp64", "mixed"]
+    if args.only == "sampler":
+        forms = ["fp64"]
     if args.all_minors and not args.only:
         forms += ["fp64_all_minors", "mixed_all_minors"]
     res, bufs = {}, {}
@@ -316,6 +385,9 @@ def main():
             del cd, kd
     if not args.no_extras and not args.only:
         extra["extras"] = batched_and_adjoint(P, torch, G, 5)
+    if args.only == "sampler" or (not args.only and not args.no_extras and not args.no_sampler):
+        extra.setdefault("extras", {}).update(
+            sampler_legs(P, torch, np, G, sigma, ((3, args.samples_k3), (5, args.samples_k5))))
     base = None
     if not args.no_cpu_baseline:
         import oracle as O

@@ -48,6 +48,8 @@ __all__ = [
     "local_phase_rotation",
     "mode_permutation",
     "input_displacement",
+    "sampler_uniforms",
+    "synthetic_parity_cumulants",
     "DISPLACEMENT_SEED",
     "DISPLACEMENT_AMP2",
 ]
@@ -246,3 +248,21 @@ def input_displacement(inst: Instance, seed: int = DISPLACEMENT_SEED,
     mu_in = math.sqrt(2.0) * np.concatenate([alpha.real, alpha.imag])
     V = interferometer_symplectic(inst.U * np.sqrt(inst.eta)[None, :])
     return V @ mu_in
+
+
+def sampler_uniforms(M: int, n: int, seed: int) -> np.ndarray:
+    """(M, n) uniforms in [0, 1) for n samples of M bits (row m: bit m + 1)."""
+    return np.random.default_rng(seed).random((M, n))
+
+
+def synthetic_parity_cumulants(M: int, K: int, seed: int) -> np.ndarray:
+    """A seeded array in the cumulant layout (orders 1..K, colex inside an
+    order), cheap at any M: order 1 ~ U[0.2, 0.7] (parity correlators of modes
+    that click with probability 0.15-0.4), order d >= 2 ~ N(0, (0.1 / 2^d)^2).
+    Not the cumulants of any particular state: a stand-in input for sampler
+    parity tests at sizes where exact cumulants are too slow to compute on a CPU."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(0.2, 0.7, size=M)]
+    for d in range(2, K + 1):
+        parts.append(rng.normal(0.0, 0.1 / 2 ** d, size=math.comb(M, d)))
+    return np.concatenate(parts)

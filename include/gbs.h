@@ -86,7 +86,8 @@ enum {
     GBS_STAGE_NORMALISE = 1,  /* per-mode normalisation of Q (GBS_MIXED)            */
     GBS_STAGE_FORWARD = 2,    /* one order's correlator/cumulant kernel             */
     GBS_STAGE_ADJOINT = 3,    /* one kernel of the vector-Jacobian product          */
-    GBS_STAGE_BATCHED = 4     /* the persistent batched kernel                      */
+    GBS_STAGE_BATCHED = 4,    /* the persistent batched kernel                      */
+    GBS_STAGE_SAMPLE = 5      /* one launch of the sampler kernel                   */
 };
 
 typedef struct {
@@ -210,6 +211,37 @@ GBS_API gbs_status gbs_autotune_batched(int32_t n, const gbs_instance* inst, int
 /* host.  Set (or, with t == NULL, clear) the cached shape used by
  * gbs_cumulants_batched for this device, order and precision. */
 GBS_API gbs_status gbs_set_tuning(int32_t max_order, int32_t flags, const gbs_tuning* t);
+
+/* Stage-2 sampler (Sec. II "The sampling algorithm"; Methods; App. C.1):
+ * nsamples click patterns x_1 .. x_M (bit n is mode n - 1) drawn one bit at a
+ * time by the chain rule, with the joint probability of the first n bits
+ * expanded in the parity cumulants kappa up to order max_order (Eq.
+ * samplecumulant) and the marginals it needs approximated by tables updated
+ * after every bit:
+ *   max_order = 3  single elision (Eqs. methprob, b, a), O(M^3) per sample;
+ *   max_order = 5  double elision (Eqs. probade, probpartialade, probelidedade,
+ *                  probdoubleelidedade), O(M^5) per sample.
+ * Bit n of sample s is 1 iff uniforms[(n-1) * nsamples + s] < p(x_n = 1 | x_<n)
+ * = (p(x_{n-1}, .., x_1) / 2 - D_n) / p(x_{n-1}, .., x_1), the expansion's value
+ * (1/2 when the previous marginal is not positive); all arithmetic is FP64.
+ *   M          1 <= M, max_order <= M; M <= 256 (max_order 3) or M <= 200 (5)
+ *   kappa      device, N(M, max_order) FP64 parity cumulants in the output layout
+ *              above (as written by gbs_cumulants with GBS_PARITY)
+ *   nsamples   >= 0 (0: nothing is launched; uniforms and bits may then be NULL)
+ *   uniforms   device, M x nsamples FP64 in [0, 1), row n-1 for bit n
+ *   bits       device, nsamples x M bytes (0/1), sample-major, overwritten
+ *   prob       device, nsamples FP64: the expansion's p(x_M, .., x_1), or NULL
+ *   cond       device, M x nsamples FP64: p(x_n = 1 | x_<n) of every step, or NULL
+ *   batch      samples per kernel launch (rounded to a multiple of 64); 0 = as
+ *              many as fit in a quarter of the free device memory.  The library
+ *              allocates the per-sample tables for one batch: 8 x (M + 1 + C(M,2)
+ *              + C(M+1,2) [+ C(M,3) for max_order 5]) bytes per sample
+ *   flags      GBS_ASYNC | GBS_TIMING (other bits: GBS_E_INVALID_ARG)
+ * Errors: GBS_E_INVALID_ARG for bad sizes, orders or null pointers;
+ * GBS_E_UNSUPPORTED for max_order other than 3 or 5. */
+GBS_API gbs_status gbs_sample(int32_t M, const double* kappa, int32_t max_order, int64_t nsamples,
+                              const double* uniforms, uint8_t* bits, double* prob, double* cond,
+                              int64_t batch, int32_t flags, void* stream);
 
 /* host.  After a call returned GBS_E_NOT_SPD (or after a GBS_ASYNC call's
  * stream completed), the order and colex rank of the first failing subset

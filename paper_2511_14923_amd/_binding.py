@@ -33,7 +33,8 @@ GBS_STAGE_NORMALISE = 1
 GBS_STAGE_FORWARD = 2
 GBS_STAGE_ADJOINT = 3
 GBS_STAGE_BATCHED = 4
-STAGE_NAMES = {0: "build_q", 1: "normalise", 2: "forward", 3: "adjoint", 4: "batched"}
+GBS_STAGE_SAMPLE = 5
+STAGE_NAMES = {0: "build_q", 1: "normalise", 2: "forward", 3: "adjoint", 4: "batched", 5: "sample"}
 
 GBS_MAX_ORDER = 5
 GBS_MAX_MODES = 2048
@@ -43,7 +44,7 @@ EXPORTS = (
     "gbs_num_subsets", "gbs_order_offset", "gbs_total_outputs", "gbs_colex_rank",
     "gbs_colex_unrank", "gbs_correlators", "gbs_cumulants", "gbs_cumulants_displaced",
     "gbs_cumulant_grad",
-    "gbs_cumulants_batched", "gbs_autotune_batched", "gbs_set_tuning", "gbs_last_error",
+    "gbs_cumulants_batched", "gbs_autotune_batched", "gbs_set_tuning", "gbs_sample", "gbs_last_error",
     "gbs_last_timings", "gbs_status_string",
 )
 
@@ -109,6 +110,8 @@ def lib() -> ctypes.CDLL:
     L.gbs_autotune_batched.restype = i32
     L.gbs_set_tuning.argtypes = [i32, i32, ctypes.POINTER(gbs_tuning)]
     L.gbs_set_tuning.restype = i32
+    L.gbs_sample.argtypes = [i32, vp, i32, i64, vp, vp, vp, vp, i64, i32, vp]
+    L.gbs_sample.restype = i32
     L.gbs_last_error.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i64)]
     L.gbs_last_error.restype = i32
     L.gbs_last_timings.argtypes = [i32, ctypes.POINTER(gbs_kernel_time)]
@@ -235,6 +238,33 @@ def gbs_cumulants_displaced(M: int, sigma: torch.Tensor, mu: torch.Tensor, max_o
                                            _ptr(cum), _stream(stream, sigma.device))
     _check(st, "gbs_cumulants_displaced")
     return corr, cum
+
+
+def _ptr_u8(t):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.uint8 \
+            or not t.is_contiguous():
+        raise ValueError("contiguous uint8 device tensor required")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def gbs_sample(M: int, kappa: torch.Tensor, max_order: int, uniforms: torch.Tensor, bits=None,
+               prob=None, cond=None, batch: int = 0, flags: int = 0, stream=None,
+               want_prob: bool = True, want_cond: bool = False) -> tuple:
+    """Sampler: uniforms is (M, n) FP64; returns (bits (n, M) uint8, prob (n,) or
+    None, cond (M, n) or None)."""
+    n = uniforms.shape[1] if uniforms.dim() == 2 else uniforms.numel() // M
+    dev = kappa.device
+    if bits is None:
+        bits = torch.empty((n, M), dtype=torch.uint8, device=dev)
+    if prob is None and want_prob:
+        prob = torch.empty(n, dtype=torch.float64, device=dev)
+    if cond is None and want_cond:
+        cond = torch.empty((M, n), dtype=torch.float64, device=dev)
+    with torch.cuda.device(dev):
+        st = lib().gbs_sample(M, _ptr(kappa), max_order, n, _ptr(uniforms), _ptr_u8(bits),
+                              _ptr(prob), _ptr(cond), batch, flags, _stream(stream, dev))
+    _check(st, "gbs_sample")
+    return bits, prob, cond
 
 
 def gbs_cumulant_grad(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0,

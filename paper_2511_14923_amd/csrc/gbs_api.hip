@@ -425,6 +425,26 @@ gbs_status gbs_cumulant_grad(int32_t M, const double* sigma, int32_t max_order, 
   return run_adjoint(M, sigma, max_order, flags, grad_corr, grad_cum, grad_sigma, stream);
 }
 
+gbs_status gbs_sample(int32_t M, const double* kappa, int32_t max_order, int64_t nsamples,
+                      const double* uniforms, uint8_t* bits, double* prob, double* cond,
+                      int64_t batch, int32_t flags, void* stream) {
+  if (M < 1 || max_order < 1 || max_order > M || nsamples < 0 || batch < 0) return GBS_E_INVALID_ARG;
+  if (flags & ~(GBS_ASYNC | GBS_TIMING)) return GBS_E_INVALID_ARG;
+  if (!kappa || (nsamples > 0 && (!uniforms || !bits))) return GBS_E_INVALID_ARG;
+  if (max_order != 3 && max_order != 5) return GBS_E_UNSUPPORTED;
+  if (M > (max_order == 3 ? 256 : 200)) return GBS_E_INVALID_ARG;
+  if (nsamples == 0) return GBS_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  timing_start_call((flags & GBS_TIMING) != 0);
+  hipError_t e = timing_begin(s, GBS_STAGE_SAMPLE, max_order);
+  if (e == hipSuccess)
+    e = run_sampler(M, max_order, kappa, nsamples, uniforms, bits, prob, cond, batch, s);
+  if (e == hipSuccess) e = timing_end(s);
+  if (e != hipSuccess) return to_status(e);
+  if (flags & GBS_ASYNC) return GBS_OK;
+  return to_status(hipStreamSynchronize(s));
+}
+
 gbs_status gbs_last_error(int32_t* order, int64_t* rank) {
   if (t_err.pending_async && t_err.host_status) {
     // valid once the stream of the last asynchronous call has completed

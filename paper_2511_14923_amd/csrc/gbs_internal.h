@@ -108,4 +108,10 @@ hipError_t launch_adjoint(int M, int K, int flags, const double* Qi, const uint6
                           double* d1, double* mbar, double* pbar, double* gsig, DeviceStatus* st,
                           hipStream_t s);
 
+// Stage-2 sampler (gbs_sampler.hip): nsamples patterns of M bits from the
+// parity cumulants kap (orders 1..K, K = 3 or 5), uniforms u (M x nsamples),
+// in launches of at most `batch` samples (0: a quarter of the free memory).
+hipError_t run_sampler(int M, int K, const double* kap, int64_t nsamples, const double* u,
+                       uint8_t* bits, double* prob, double* cond, int64_t batch, hipStream_t s);
+
 }  // namespace gbs

@@ -85,6 +85,19 @@ def test_invalid_arguments_rejected_on_host():
         P.GBS_E_INVALID_ARG
     assert lib.gbs_cumulants_displaced(10, fake, fake, 3, P.GBS_MIXED, None, fake, None) == \
         P.GBS_E_UNSUPPORTED
+    # sampler: orders 3 and 5 only, mode limits, required buffers, flags
+    S = lib.gbs_sample
+    assert S(10, fake, 4, 8, fake, fake, None, None, 0, 0, None) == P.GBS_E_UNSUPPORTED
+    assert S(10, fake, 3, -1, fake, fake, None, None, 0, 0, None) == P.GBS_E_INVALID_ARG
+    assert S(4, fake, 5, 8, fake, fake, None, None, 0, 0, None) == P.GBS_E_INVALID_ARG
+    assert S(257, fake, 3, 8, fake, fake, None, None, 0, 0, None) == P.GBS_E_INVALID_ARG
+    assert S(201, fake, 5, 8, fake, fake, None, None, 0, 0, None) == P.GBS_E_INVALID_ARG
+    assert S(10, None, 3, 8, fake, fake, None, None, 0, 0, None) == P.GBS_E_INVALID_ARG
+    assert S(10, fake, 3, 8, None, fake, None, None, 0, 0, None) == P.GBS_E_INVALID_ARG
+    assert S(10, fake, 3, 8, fake, None, None, None, 0, 0, None) == P.GBS_E_INVALID_ARG
+    assert S(10, fake, 3, 8, fake, fake, None, None, -1, 0, None) == P.GBS_E_INVALID_ARG
+    assert S(10, fake, 3, 8, fake, fake, None, None, 0, P.GBS_PARITY, None) == P.GBS_E_INVALID_ARG
+    assert S(10, fake, 3, 0, None, None, None, None, 0, 0, None) == P.GBS_OK  # nothing to do
 
 
 def test_status_strings():
