@@ -43,6 +43,8 @@ namespace {
 // barriers.
 template <int K>
 constexpr int samp_waves() { return K == 5 ? 16 : 4; }
+// i values per unit of the blocked order-5 sum
+constexpr int kIB = 8;
 
 // Entry counts of the tables (1-based bit indices):
 //   p(a)         a = 0..M                                  entry a
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(64 * kSampWaves) void sampler_kernel(
         if constexpr (K == 3) {
           D += flip(0.125 * kap[o3 + r2(i) + r1(j)] * t.pp(n - 1, i + 1) * t.p1(i - 1, j), sij);
         } else {
-          const uint32_t o4 = ko.off[4] + r4(n), o5 = ko.off[5] + r5(n);
+          const uint32_t o4 = ko.off[4] + r4(n);
           double v = 0.125 * kap[o3 + r2(i) + r1(j)] * t.p2(n - 1, i, j);
           const double A = t.pp(n - 1, i + 1);
           double a4 = 0.0;
@@ -172,21 +174,46 @@ __global__ __launch_bounds__(64 * kSampWaves) void sampler_kernel(
 #pragma unroll 4
           for (int k = 1; k < j; ++k)
             a4 += flip(kap[ok4 + r1(k)] * t.p2(i - 1, j, k), x.get(k));
-          double a5 = 0.0;
-          if (j >= 3) {
-            const double B = t.pp(i - 1, j + 1);
-            for (int k = 2; k < j; ++k) {
-              double a5k = 0.0;
-              const uint32_t ok = o5 + r4(i) + r3(j) + r2(k);
-#pragma unroll 4
-              for (int l = 1; l < k; ++l)
-                a5k += flip(kap[ok + r1(l)] * t.p2(j - 1, k, l), x.get(l));
-              a5 += flip(a5k, x.get(k));
-            }
-            a5 *= B;
-          }
-          v += A * fma(a5, 1.0 / 32.0, a4 * (1.0 / 16.0));
+          v += A * a4 * (1.0 / 16.0);
           D += flip(v, sij);
+        }
+      }
+    }
+    if constexpr (K == 5) {
+      // order 5: sum_{i>j>k>l} gamma_{ijkln} p+(n-1..i+1) p+(i-1..j+1) p2(j-1; k, l).
+      // Units (j, block of kIB consecutive i > j) are dealt round-robin; a unit
+      // keeps chi_i p+(n-1..i+1) p+(i-1..j+1) of its i in registers and reads
+      // every p2(j-1; k, l) once for all of them.
+      const uint32_t o5 = ko.off[5] + r5(n);
+      int unit = 0;
+      for (int j = 3; j < n - 1; ++j) {
+        const int nblk = (n - 1 - j + kIB - 1) / kIB;
+        for (int b = 0; b < nblk; ++b, ++unit) {
+          if (unit % kSampWaves != w) continue;
+          double wv[kIB];
+          uint32_t kb[kIB];
+#pragma unroll
+          for (int ib = 0; ib < kIB; ++ib) {
+            const int i = j + 1 + b * kIB + ib;
+            const bool in = i < n;
+            const int ic = in ? i : n - 1;  // a valid cumulant index; its weight is 0
+            kb[ib] = o5 + r4(ic) + r3(j);
+            wv[ib] = in ? flip(t.pp(n - 1, i + 1) * t.pp(i - 1, j + 1), x.get(i)) : 0.0;
+          }
+          double acc = 0.0;
+          for (int k = 2; k < j; ++k) {
+            double ak = 0.0;
+            const uint32_t rk = r2(k);
+#pragma unroll 2
+            for (int l = 1; l < k; ++l) {
+              double kw = 0.0;
+#pragma unroll
+              for (int ib = 0; ib < kIB; ++ib) kw = fma(kap[kb[ib] + rk + r1(l)], wv[ib], kw);
+              ak += flip(kw * t.p2(j - 1, k, l), x.get(l));
+            }
+            acc += flip(ak, x.get(k));
+          }
+          D += flip(acc * (1.0 / 32.0), x.get(j));
         }
       }
     }
@@ -307,6 +334,9 @@ hipError_t run_sampler(int M, int K, const double* kap, int64_t nsamples, const 
     batch = samp_batch(M, K, free_b / 4);
   }
   batch = std::max<int64_t>(64, std::min<int64_t>(batch, (nsamples + 63) / 64 * 64));
+  // equal launches: a small last launch would run for as long as a full one
+  const int64_t nlaunch = (nsamples + batch - 1) / batch;
+  batch = ((nsamples + nlaunch - 1) / nlaunch + 63) / 64 * 64;
   const uint64_t ldt = (uint64_t)(batch + 63) / 64 * 64;
   void* scratch = nullptr;
   hipError_t e = hipMallocAsync(&scratch, (size_t)L.entries() * ldt * sizeof(double), s);
