@@ -241,6 +241,8 @@ def sampler_legs(P, torch, np, G, sigma, counts):
         wall = time.perf_counter() - t0
         kms = sum(ms for st, _, ms in P.gbs_last_timings() if st == "sample")
         terms = sampler_terms(M, K_) * n
+        if K_ == 3:
+            keep = bits
         out[f"sample_k{K_}_m144"] = {
             "samples": n, "seconds": wall, "samples_per_s": n / wall, "kernel_ms": kms,
             "terms_per_sample": sampler_terms(M, K_), "terms_per_s": terms / (kms * 1e-3),
@@ -249,6 +251,10 @@ def sampler_legs(P, torch, np, G, sigma, counts):
             "mean_clicks": float(bits.float().mean().item() * M),
             "method": "single elision" if K_ == 3 else "double elision"}
         del kap, u, bits, prob
+    # sample statistics on the single-elision samples: unbiased click cumulants
+    # of orders 1..5 and their Pearson coefficient with the stage-1 ground truth
+    out["validate_m144"] = estimator_leg(P, torch, sigma, keep)
+    del keep
     # the C oracle on the host cores, same sizes, seeded synthetic cumulants
     import oracle as O
     from oracle import sampler as S
@@ -263,6 +269,28 @@ def sampler_legs(P, torch, np, G, sigma, counts):
             "kind": "oracle"}
         log(f"[bench] sampler K={K_} cpu oracle: {n} samples in {dt:.1f} s")
     return out
+
+
+def estimator_leg(P, torch, sigma, bits):
+    n = bits.shape[0]
+    P.gbs_sample_cumulants(bits[:64].contiguous(), 2)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    est = P.gbs_sample_cumulants(bits, K, flags=P.GBS_TIMING)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = sum(ms for st, _, ms in P.gbs_last_timings() if st == "estimate")
+    truth = P.gbs_cumulants(M, sigma, K, 0, want_corr=False)[1]
+    rs = {}
+    for d in range(1, K + 1):
+        a, b = P.gbs_order_offset(M, d), P.gbs_order_offset(M, d + 1)
+        rs[str(d)] = float(P.gbs_pearson(est[a:b].contiguous(), truth[a:b].contiguous()).item())
+    log(f"[bench] estimator: {n} samples, orders 1..{K} in {wall:.3f} s; pearson {rs}")
+    N = P.gbs_total_outputs(M, K)
+    return {"samples": n, "subsets": N, "seconds": wall, "kernel_ms": kms,
+            "subset_samples_per_s": N * n / wall,
+            "pearson_vs_ground_truth": rs,
+            "note": "unbiased click cumulants of the single-elision samples vs stage-1 click cumulants"}
 
 
 def cpu_baseline(np, O, G, inst, seconds):

@@ -87,7 +87,8 @@ enum {
     GBS_STAGE_FORWARD = 2,    /* one order's correlator/cumulant kernel             */
     GBS_STAGE_ADJOINT = 3,    /* one kernel of the vector-Jacobian product          */
     GBS_STAGE_BATCHED = 4,    /* the persistent batched kernel                      */
-    GBS_STAGE_SAMPLE = 5      /* one launch of the sampler kernel                   */
+    GBS_STAGE_SAMPLE = 5,     /* one launch of the sampler kernel                   */
+    GBS_STAGE_ESTIMATE = 6    /* gbs_sample_cumulants or gbs_pearson (whole call)   */
 };
 
 typedef struct {
@@ -242,6 +243,35 @@ GBS_API gbs_status gbs_set_tuning(int32_t max_order, int32_t flags, const gbs_tu
 GBS_API gbs_status gbs_sample(int32_t M, const double* kappa, int32_t max_order, int64_t nsamples,
                               const double* uniforms, uint8_t* bits, double* prob, double* cond,
                               int64_t batch, int32_t flags, void* stream);
+
+/* Click cumulants estimated from samples (App. F, "Click cumulants, Pearson and
+ * Spearman coefficients", Eq. cumulants_test_def): for every S with
+ * 1 <= |S| <= max_order, the unbiased estimate of kappa~(S) in which each
+ * product of |pi| click moments of the partition sum is averaged over ordered
+ * tuples of distinct samples (k-statistics).  Computed from the power sums
+ * s_B (samples in which every mode of B clicked) of all subsets, as bit-matrix
+ * products of per-mode bit columns; FP64 combination.
+ *   M          1 <= M <= 256, max_order <= M
+ *   nsamples   max_order <= nsamples < 2^32
+ *   bits       device, nsamples x M bytes (0/1), sample-major (as gbs_sample writes)
+ *   max_order  1..GBS_MAX_ORDER
+ *   cum        device, N(M, max_order) FP64, output layout above, overwritten
+ *   flags      GBS_ASYNC | GBS_TIMING
+ * The library allocates M * ceil(nsamples / 64) * 8 bytes of bit columns plus
+ * 4 bytes per subset of counts. */
+GBS_API gbs_status gbs_sample_cumulants(int32_t M, int64_t nsamples, const uint8_t* bits,
+                                        int32_t max_order, double* cum, int32_t flags,
+                                        void* stream);
+
+/* Pearson correlation coefficient of x and y (Eq. pearson_correlation):
+ * sum (x - <x>)(y - <y>) / sqrt(sum (x - <x>)^2 sum (y - <y>)^2), two passes
+ * of FP64 reductions in a fixed order (deterministic).
+ *   n      >= 2
+ *   x, y   device, n FP64 each
+ *   r      device, one FP64, overwritten
+ *   flags  GBS_ASYNC | GBS_TIMING */
+GBS_API gbs_status gbs_pearson(int64_t n, const double* x, const double* y, double* r,
+                               int32_t flags, void* stream);
 
 /* host.  After a call returned GBS_E_NOT_SPD (or after a GBS_ASYNC call's
  * stream completed), the order and colex rank of the first failing subset

@@ -34,7 +34,9 @@ GBS_STAGE_FORWARD = 2
 GBS_STAGE_ADJOINT = 3
 GBS_STAGE_BATCHED = 4
 GBS_STAGE_SAMPLE = 5
-STAGE_NAMES = {0: "build_q", 1: "normalise", 2: "forward", 3: "adjoint", 4: "batched", 5: "sample"}
+GBS_STAGE_ESTIMATE = 6
+STAGE_NAMES = {0: "build_q", 1: "normalise", 2: "forward", 3: "adjoint", 4: "batched", 5: "sample",
+               6: "estimate"}
 
 GBS_MAX_ORDER = 5
 GBS_MAX_MODES = 2048
@@ -44,7 +46,8 @@ EXPORTS = (
     "gbs_num_subsets", "gbs_order_offset", "gbs_total_outputs", "gbs_colex_rank",
     "gbs_colex_unrank", "gbs_correlators", "gbs_cumulants", "gbs_cumulants_displaced",
     "gbs_cumulant_grad",
-    "gbs_cumulants_batched", "gbs_autotune_batched", "gbs_set_tuning", "gbs_sample", "gbs_last_error",
+    "gbs_cumulants_batched", "gbs_autotune_batched", "gbs_set_tuning", "gbs_sample",
+    "gbs_sample_cumulants", "gbs_pearson", "gbs_last_error",
     "gbs_last_timings", "gbs_status_string",
 )
 
@@ -112,6 +115,10 @@ def lib() -> ctypes.CDLL:
     L.gbs_set_tuning.restype = i32
     L.gbs_sample.argtypes = [i32, vp, i32, i64, vp, vp, vp, vp, i64, i32, vp]
     L.gbs_sample.restype = i32
+    L.gbs_sample_cumulants.argtypes = [i32, i64, vp, i32, vp, i32, vp]
+    L.gbs_sample_cumulants.restype = i32
+    L.gbs_pearson.argtypes = [i64, vp, vp, vp, i32, vp]
+    L.gbs_pearson.restype = i32
     L.gbs_last_error.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i64)]
     L.gbs_last_error.restype = i32
     L.gbs_last_timings.argtypes = [i32, ctypes.POINTER(gbs_kernel_time)]
@@ -265,6 +272,28 @@ def gbs_sample(M: int, kappa: torch.Tensor, max_order: int, uniforms: torch.Tens
                               _ptr(prob), _ptr(cond), batch, flags, _stream(stream, dev))
     _check(st, "gbs_sample")
     return bits, prob, cond
+
+
+def gbs_sample_cumulants(bits: torch.Tensor, max_order: int, cum=None, flags: int = 0,
+                         stream=None) -> torch.Tensor:
+    """Unbiased click cumulants of orders 1..max_order from samples (n, M) uint8."""
+    n, M = bits.shape
+    cum = _out(cum, max(gbs_total_outputs(M, max_order), 0), bits)
+    with torch.cuda.device(bits.device):
+        st = lib().gbs_sample_cumulants(M, n, _ptr_u8(bits), max_order, _ptr(cum), flags,
+                                        _stream(stream, bits.device))
+    _check(st, "gbs_sample_cumulants")
+    return cum
+
+
+def gbs_pearson(x: torch.Tensor, y: torch.Tensor, r=None, flags: int = 0, stream=None) -> torch.Tensor:
+    """Pearson coefficient of two device FP64 vectors (a one-element tensor)."""
+    if r is None:
+        r = torch.empty(1, dtype=torch.float64, device=x.device)
+    with torch.cuda.device(x.device):
+        st = lib().gbs_pearson(x.numel(), _ptr(x), _ptr(y), _ptr(r), flags, _stream(stream, x.device))
+    _check(st, "gbs_pearson")
+    return r
 
 
 def gbs_cumulant_grad(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0,

@@ -445,6 +445,39 @@ gbs_status gbs_sample(int32_t M, const double* kappa, int32_t max_order, int64_t
   return to_status(hipStreamSynchronize(s));
 }
 
+gbs_status gbs_sample_cumulants(int32_t M, int64_t nsamples, const uint8_t* bits,
+                                int32_t max_order, double* cum, int32_t flags, void* stream) {
+  if (M < 1 || M > 256 || max_order < 1 || max_order > GBS_MAX_ORDER || max_order > M)
+    return GBS_E_INVALID_ARG;
+  if (nsamples < max_order || nsamples >= (int64_t)1 << 32 || !bits || !cum) return GBS_E_INVALID_ARG;
+  if (flags & ~(GBS_ASYNC | GBS_TIMING)) return GBS_E_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e;
+  DeviceContext* ctx = current_context(&e);
+  if (!ctx) return to_status(e);
+  timing_start_call((flags & GBS_TIMING) != 0);
+  e = timing_begin(s, GBS_STAGE_ESTIMATE, max_order);
+  if (e == hipSuccess) e = run_sample_cumulants(M, nsamples, bits, max_order, ctx->binom, cum, s);
+  if (e == hipSuccess) e = timing_end(s);
+  if (e != hipSuccess) return to_status(e);
+  if (flags & GBS_ASYNC) return GBS_OK;
+  return to_status(hipStreamSynchronize(s));
+}
+
+gbs_status gbs_pearson(int64_t n, const double* x, const double* y, double* r, int32_t flags,
+                       void* stream) {
+  if (n < 2 || !x || !y || !r) return GBS_E_INVALID_ARG;
+  if (flags & ~(GBS_ASYNC | GBS_TIMING)) return GBS_E_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  timing_start_call((flags & GBS_TIMING) != 0);
+  hipError_t e = timing_begin(s, GBS_STAGE_ESTIMATE, 0);
+  if (e == hipSuccess) e = run_pearson((uint64_t)n, x, y, r, s);
+  if (e == hipSuccess) e = timing_end(s);
+  if (e != hipSuccess) return to_status(e);
+  if (flags & GBS_ASYNC) return GBS_OK;
+  return to_status(hipStreamSynchronize(s));
+}
+
 gbs_status gbs_last_error(int32_t* order, int64_t* rank) {
   if (t_err.pending_async && t_err.host_status) {
     // valid once the stream of the last asynchronous call has completed

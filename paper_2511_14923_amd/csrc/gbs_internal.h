@@ -114,4 +114,11 @@ hipError_t launch_adjoint(int M, int K, int flags, const double* Qi, const uint6
 hipError_t run_sampler(int M, int K, const double* kap, int64_t nsamples, const double* u,
                        uint8_t* bits, double* prob, double* cond, int64_t batch, hipStream_t s);
 
+// Sample statistics (gbs_estimator.hip): unbiased click cumulants of orders
+// 1..K from N samples (bits N x M), written in the output layout; Pearson
+// coefficient of two device arrays of length n, written to r (device).
+hipError_t run_sample_cumulants(int M, int64_t N, const uint8_t* bits, int K,
+                                const uint64_t* binom, double* out, hipStream_t s);
+hipError_t run_pearson(uint64_t n, const double* x, const double* y, double* r, hipStream_t s);
+
 }  // namespace gbs

@@ -98,6 +98,17 @@ def test_invalid_arguments_rejected_on_host():
     assert S(10, fake, 3, 8, fake, fake, None, None, -1, 0, None) == P.GBS_E_INVALID_ARG
     assert S(10, fake, 3, 8, fake, fake, None, None, 0, P.GBS_PARITY, None) == P.GBS_E_INVALID_ARG
     assert S(10, fake, 3, 0, None, None, None, None, 0, 0, None) == P.GBS_OK  # nothing to do
+    # sample statistics
+    C = lib.gbs_sample_cumulants
+    assert C(0, 10, fake, 1, fake, 0, None) == P.GBS_E_INVALID_ARG
+    assert C(257, 10, fake, 1, fake, 0, None) == P.GBS_E_INVALID_ARG
+    assert C(10, 3, fake, 4, fake, 0, None) == P.GBS_E_INVALID_ARG  # fewer samples than the order
+    assert C(10, 10, fake, 6, fake, 0, None) == P.GBS_E_INVALID_ARG
+    assert C(10, 10, None, 2, fake, 0, None) == P.GBS_E_INVALID_ARG
+    assert C(10, 10, fake, 2, None, 0, None) == P.GBS_E_INVALID_ARG
+    assert C(10, 1 << 32, fake, 2, fake, 0, None) == P.GBS_E_INVALID_ARG
+    assert lib.gbs_pearson(1, fake, fake, fake, 0, None) == P.GBS_E_INVALID_ARG
+    assert lib.gbs_pearson(5, fake, None, fake, 0, None) == P.GBS_E_INVALID_ARG
 
 
 def test_status_strings():
