@@ -293,6 +293,33 @@ def estimator_leg(P, torch, sigma, bits):
             "note": "unbiased click cumulants of the single-elision samples vs stage-1 click cumulants"}
 
 
+def shard_leg(P, torch, G, inst):
+    """One GPU's share of the pseudo-photon-number-resolving workload: M = 1152
+    (each of the 144 modes split over 8 detectors), order-5 outputs of a colex
+    rank range as large as the whole M = 144 order-5 launch, by the tree
+    kernel from Q alone."""
+    M_ = 1152
+    sig = torch.from_numpy(G.pseudo_pnr_covariance(inst.sigma, 8)).to("cuda:0")
+    total = math.comb(M_, 5)
+    cnt = math.comb(M, 5)
+    r0 = total // 2
+    corr = torch.empty(cnt, dtype=torch.float64, device="cuda:0")
+    cum = torch.empty(cnt, dtype=torch.float64, device="cuda:0")
+    P.gbs_cumulants_shard(M_, sig, 5, r0, 65536, 0, corr=corr[:65536], cum=cum[:65536])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.gbs_cumulants_shard(M_, sig, 5, r0, cnt, P.GBS_TIMING, corr=corr, cum=cum)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = sum(ms for st, order, ms in P.gbs_last_timings() if st == "forward")
+    rate = cnt / (kms * 1e-3)
+    log(f"[bench] shard M=1152 order 5: {cnt} subsets in {kms:.1f} ms")
+    return {"M": M_, "order": 5, "rank0": r0, "subsets": cnt, "seconds": wall, "kernel_ms": kms,
+            "subsets_per_s": rate, "order5_total": total,
+            "full_order5_one_gpu_s": total / rate, "full_order5_eight_gpus_s": total / rate / 8,
+            "kernel": "tree kernel (all 31 minors per subset), one shard of the colex rank range"}
+
+
 def cpu_baseline(np, O, G, inst, seconds):
     """The C oracle on the host cores over a random sample of the workload's
     subsets (all orders, in proportion to their counts)."""
@@ -418,6 +445,10 @@ def main():
             del cd, kd
     if not args.no_extras and not args.only:
         extra["extras"] = batched_and_adjoint(P, torch, G, 5)
+        for form in list(bufs):
+            del bufs[form]
+        torch.cuda.empty_cache()
+        extra["extras"]["shard_m1152_k5"] = shard_leg(P, torch, G, inst)
     if args.only == "sampler" or (not args.only and not args.no_extras and not args.no_sampler):
         extra.setdefault("extras", {}).update(
             sampler_legs(P, torch, np, G, sigma, ((3, args.samples_k3), (5, args.samples_k5))))

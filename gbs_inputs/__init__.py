@@ -49,6 +49,7 @@ __all__ = [
     "mode_permutation",
     "input_displacement",
     "sampler_uniforms",
+    "pseudo_pnr_covariance",
     "synthetic_parity_cumulants",
     "DISPLACEMENT_SEED",
     "DISPLACEMENT_AMP2",
@@ -266,3 +267,21 @@ def synthetic_parity_cumulants(M: int, K: int, seed: int) -> np.ndarray:
     for d in range(2, K + 1):
         parts.append(rng.normal(0.0, 0.1 / 2 ** d, size=math.comb(M, d)))
     return np.concatenate(parts)
+
+
+def pseudo_pnr_covariance(sigma: np.ndarray, k: int = 8) -> np.ndarray:
+    """Covariance (xxpp, hbar = 1) after every mode of ``sigma`` is split evenly
+    over k threshold detectors (pseudo-photon-number resolution): mode g and
+    k - 1 vacua enter a k x k discrete Fourier transform whose outputs are
+    modes g k .. g k + k - 1.  M modes become M k (144 -> 1152 for k = 8)."""
+    M0 = sigma.shape[0] // 2
+    M = M0 * k
+    sin = 0.5 * np.eye(2 * M)
+    sig_idx = np.arange(M0) * k  # input index of signal g: g k + 0
+    idx = np.concatenate([sig_idx, sig_idx + M])
+    sin[np.ix_(idx, idx)] = sigma
+    F = np.exp(2j * math.pi * np.outer(np.arange(k), np.arange(k)) / k) / math.sqrt(k)
+    U = np.kron(np.eye(M0), F)
+    W = interferometer_symplectic(U)
+    out = W @ sin @ W.T
+    return 0.5 * (out + out.T)

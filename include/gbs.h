@@ -157,6 +157,24 @@ GBS_API gbs_status gbs_cumulants_displaced(int32_t M, const double* sigma, const
                                    int32_t max_order, int32_t flags, double* corr, double* cum,
                                    void* stream);
 
+/* One shard of one order: the correlators and cumulants of the order-`order`
+ * subsets with colex ranks rank0 .. rank0 + count - 1 (in rank order), each
+ * evaluated from Q alone by the all-minors kernel (every principal minor of
+ * Q_S, no lower-order tables), so that disjoint rank ranges are independent
+ * work: the unit by which the computation splits across devices for large M
+ * (e.g. M = 1152 pseudo-photon-number-resolving detection, C(1152, 5) = 1.7e13
+ * order-5 subsets).  Same definitions and tolerance as gbs_cumulants.
+ *   order        1 <= order <= min(GBS_MAX_ORDER, M)
+ *   rank0, count rank0 >= 0, count >= 0, rank0 + count <= C(M, order)
+ *   corr, cum    device, count FP64 each (either may be NULL, not both)
+ *   flags        GBS_CLICK/GBS_PARITY | GBS_ASYNC | GBS_TIMING (GBS_MIXED and
+ *                GBS_ALL_MINORS give GBS_E_UNSUPPORTED)
+ * Other arguments and errors as gbs_cumulants; gbs_last_error reports the
+ * global colex rank of a failing subset. */
+GBS_API gbs_status gbs_cumulants_shard(int32_t M, const double* sigma, int32_t order, int64_t rank0,
+                                       int64_t count, int32_t flags, double* corr, double* cum,
+                                       void* stream);
+
 /* Vector-Jacobian product of gbs_cumulants (FP64 only; GBS_MIXED gives
  * GBS_E_UNSUPPORTED):
  *   grad_sigma[i][j] = sum_S grad_corr[S] d corr[S]/d sigma_ij

@@ -45,6 +45,7 @@ GBS_MAX_MODES = 2048
 EXPORTS = (
     "gbs_num_subsets", "gbs_order_offset", "gbs_total_outputs", "gbs_colex_rank",
     "gbs_colex_unrank", "gbs_correlators", "gbs_cumulants", "gbs_cumulants_displaced",
+    "gbs_cumulants_shard",
     "gbs_cumulant_grad",
     "gbs_cumulants_batched", "gbs_autotune_batched", "gbs_set_tuning", "gbs_sample",
     "gbs_sample_cumulants", "gbs_pearson", "gbs_last_error",
@@ -104,6 +105,8 @@ def lib() -> ctypes.CDLL:
     L.gbs_cumulants.restype = i32
     L.gbs_cumulants_displaced.argtypes = [i32, vp, vp, i32, i32, vp, vp, vp]
     L.gbs_cumulants_displaced.restype = i32
+    L.gbs_cumulants_shard.argtypes = [i32, vp, i32, i64, i64, i32, vp, vp, vp]
+    L.gbs_cumulants_shard.restype = i32
     L.gbs_cumulant_grad.argtypes = [i32, vp, i32, i32, vp, vp, vp, vp]
     L.gbs_cumulant_grad.restype = i32
     L.gbs_cumulants_batched.argtypes = [i32, ctypes.POINTER(gbs_instance), i32, i32, vp]
@@ -244,6 +247,19 @@ def gbs_cumulants_displaced(M: int, sigma: torch.Tensor, mu: torch.Tensor, max_o
         st = lib().gbs_cumulants_displaced(M, _ptr(sigma), _ptr(mu), max_order, flags, _ptr(corr),
                                            _ptr(cum), _stream(stream, sigma.device))
     _check(st, "gbs_cumulants_displaced")
+    return corr, cum
+
+
+def gbs_cumulants_shard(M: int, sigma: torch.Tensor, order: int, rank0: int, count: int,
+                        flags: int = 0, corr=None, cum=None, stream=None,
+                        want_corr: bool = True) -> tuple:
+    if want_corr:
+        corr = _out(corr, count, sigma)
+    cum = _out(cum, count, sigma)
+    with torch.cuda.device(sigma.device):
+        st = lib().gbs_cumulants_shard(M, _ptr(sigma), order, rank0, count, flags, _ptr(corr),
+                                       _ptr(cum), _stream(stream, sigma.device))
+    _check(st, "gbs_cumulants_shard")
     return corr, cum
 
 

@@ -278,6 +278,37 @@ gbs_status run_forward(int32_t M, const double* sigma, const double* mu, int32_t
   return finish_call(sc.st, scratch, flags, s);
 }
 
+gbs_status run_shard(int32_t M, const double* sigma, int32_t d, int64_t rank0, int64_t count,
+                     int32_t flags, double* corr, double* cum, void* stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e;
+  DeviceContext* ctx = current_context(&e);
+  if (!ctx) return to_status(e);
+  const size_t oQ = 0, oSt = align256(4 * (size_t)M * M * sizeof(double));
+  void* scratch = nullptr;
+  e = hipMallocAsync(&scratch, oSt + align256(sizeof(DeviceStatus)), s);
+  if (e != hipSuccess) return to_status(e);
+  double* Qi = reinterpret_cast<double*>(static_cast<char*>(scratch) + oQ);
+  DeviceStatus* st = reinterpret_cast<DeviceStatus*>(static_cast<char*>(scratch) + oSt);
+  t_err.order = 0;
+  t_err.rank = -1;
+  timing_start_call((flags & GBS_TIMING) != 0);
+  e = launch_clear_status(st, s);
+  if (e == hipSuccess) e = timing_begin(s, GBS_STAGE_BUILD_Q, 0);
+  if (e == hipSuccess) e = launch_build_q(sigma, M, Qi, s);
+  if (e == hipSuccess) e = timing_end(s);
+  if (e == hipSuccess) e = timing_begin(s, GBS_STAGE_FORWARD, d);
+  if (e == hipSuccess)
+    e = launch_forward_range(d, M, flags, Qi, ctx->binom, (uint64_t)rank0, (uint64_t)count, corr,
+                             cum, st, s);
+  if (e == hipSuccess) e = timing_end(s);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(scratch, s);
+    return to_status(e);
+  }
+  return finish_call(st, scratch, flags, s);
+}
+
 gbs_status run_adjoint(int32_t M, const double* sigma, int32_t K, int32_t flags,
                        const double* gm, const double* gk, double* gsig, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -415,6 +446,16 @@ gbs_status gbs_cumulants_displaced(int32_t M, const double* sigma, const double*
   if (!valid_problem(M, max_order, flags) || !sigma || !mu || !cum) return GBS_E_INVALID_ARG;
   if (flags & GBS_MIXED) return GBS_E_UNSUPPORTED;
   return run_forward(M, sigma, mu, max_order, flags, corr, cum, stream);
+}
+
+gbs_status gbs_cumulants_shard(int32_t M, const double* sigma, int32_t order, int64_t rank0,
+                               int64_t count, int32_t flags, double* corr, double* cum,
+                               void* stream) {
+  if (!valid_problem(M, order, flags) || !sigma || (!corr && !cum)) return GBS_E_INVALID_ARG;
+  if (rank0 < 0 || count < 0) return GBS_E_INVALID_ARG;
+  if ((uint64_t)rank0 + (uint64_t)count > host_binom(M, order)) return GBS_E_INVALID_ARG;
+  if (flags & (GBS_MIXED | GBS_ALL_MINORS)) return GBS_E_UNSUPPORTED;
+  return run_shard(M, sigma, order, rank0, count, flags, corr, cum, stream);
 }
 
 gbs_status gbs_cumulant_grad(int32_t M, const double* sigma, int32_t max_order, int32_t flags,

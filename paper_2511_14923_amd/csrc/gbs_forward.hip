@@ -34,7 +34,7 @@ namespace gbs {
 template <int D, int CONV, bool WRITE_CORR, bool WRITE_CUM, bool LDS_BIN, bool DISP>
 __global__ __launch_bounds__(256) void forward_fp64_kernel(const double* __restrict__ Qi,
                                                            const double* __restrict__ mi, int M,
-                                                           uint64_t count,
+                                                           uint64_t rank0, uint64_t count,
                                                            const uint64_t* __restrict__ binom,
                                                            double* __restrict__ corr,
                                                            double* __restrict__ cum,
@@ -59,12 +59,12 @@ __global__ __launch_bounds__(256) void forward_fp64_kernel(const double* __restr
   for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < count; r += stride) {
 
   int s[D];
-  colex_unrank<D>(r, M, bin, ld, s);
+  colex_unrank<D>(rank0 + r, M, bin, ld, s);
   double mS, kS, pS;
   bool bad = false;
   if constexpr (DISP) subset_fp64_disp<D, CONV, WRITE_CUM>(Qi, mi, M, s, mS, kS, pS, bad);
   else subset_fp64<D, CONV, WRITE_CUM>(Qi, M, s, mS, kS, pS, bad);
-  if (bad) latch_failure(st, D, (int64_t)r);
+  if (bad) latch_failure(st, D, (int64_t)(rank0 + r));
   if (ptab) ptab[r] = pS;
   if constexpr (WRITE_CORR) corr[r] = mS;
   if constexpr (WRITE_CUM) cum[r] = kS;
@@ -139,18 +139,18 @@ hipError_t launch_clear_status(DeviceStatus* st, hipStream_t s) {
 template <int D, int CONV, bool WC, bool WK, bool DISP>
 static hipError_t launch_fp64_t(int M, const double* Qi, const double* mi, const uint64_t* binom,
                                 double* corr, double* cum, double* ptab, DeviceStatus* st,
-                                hipStream_t s) {
-  const uint64_t count = host_binom(M, D);
+                                hipStream_t s, uint64_t rank0 = 0, uint64_t count = ~0ull) {
+  if (count == ~0ull) count = host_binom(M, D);
   if (count == 0) return hipSuccess;
   const int block = 256;
   const uint64_t grid = std::min<uint64_t>((count + block - 1) / block, kMaxGrid);
   const size_t lds = (size_t)(D + 1) * (M + 1) * sizeof(uint64_t);
   if (lds <= 48 * 1024) {
     hipLaunchKernelGGL((forward_fp64_kernel<D, CONV, WC, WK, true, DISP>), dim3((unsigned)grid),
-                       dim3(block), lds, s, Qi, mi, M, count, binom, corr, cum, ptab, st);
+                       dim3(block), lds, s, Qi, mi, M, rank0, count, binom, corr, cum, ptab, st);
   } else {
     hipLaunchKernelGGL((forward_fp64_kernel<D, CONV, WC, WK, false, DISP>), dim3((unsigned)grid),
-                       dim3(block), 0, s, Qi, mi, M, count, binom, corr, cum, ptab, st);
+                       dim3(block), 0, s, Qi, mi, M, rank0, count, binom, corr, cum, ptab, st);
   }
   return hipGetLastError();
 }
@@ -198,6 +198,37 @@ hipError_t launch_forward(int d, int M, int flags, const double* Qi, const doubl
     case 3: return launch_fp64_c<3>(M, flags, Qi, mi, binom, corr, cum, ptab, st, s);
     case 4: return launch_fp64_c<4>(M, flags, Qi, mi, binom, corr, cum, ptab, st, s);
     case 5: return launch_fp64_c<5>(M, flags, Qi, mi, binom, corr, cum, ptab, st, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// One order's outputs for the colex ranks rank0 .. rank0 + count - 1 by the
+// tree kernel (no lower-order tables: every rank range is independent).
+template <int D>
+static hipError_t launch_range_d(int M, int flags, const double* Qi, const uint64_t* binom,
+                                 uint64_t rank0, uint64_t count, double* corr, double* cum,
+                                 DeviceStatus* st, hipStream_t s) {
+  const bool par = (flags & GBS_PARITY) != 0;
+  if (corr && cum)
+    return par ? launch_fp64_t<D, GBS_PARITY, true, true, false>(M, Qi, nullptr, binom, corr, cum, nullptr, st, s, rank0, count)
+               : launch_fp64_t<D, GBS_CLICK, true, true, false>(M, Qi, nullptr, binom, corr, cum, nullptr, st, s, rank0, count);
+  if (corr)
+    return par ? launch_fp64_t<D, GBS_PARITY, true, false, false>(M, Qi, nullptr, binom, corr, cum, nullptr, st, s, rank0, count)
+               : launch_fp64_t<D, GBS_CLICK, true, false, false>(M, Qi, nullptr, binom, corr, cum, nullptr, st, s, rank0, count);
+  return par ? launch_fp64_t<D, GBS_PARITY, false, true, false>(M, Qi, nullptr, binom, corr, cum, nullptr, st, s, rank0, count)
+             : launch_fp64_t<D, GBS_CLICK, false, true, false>(M, Qi, nullptr, binom, corr, cum, nullptr, st, s, rank0, count);
+}
+
+hipError_t launch_forward_range(int d, int M, int flags, const double* Qi, const uint64_t* binom,
+                                uint64_t rank0, uint64_t count, double* corr, double* cum,
+                                DeviceStatus* st, hipStream_t s) {
+  if (count == 0 || (!corr && !cum)) return hipSuccess;
+  switch (d) {
+    case 1: return launch_range_d<1>(M, flags, Qi, binom, rank0, count, corr, cum, st, s);
+    case 2: return launch_range_d<2>(M, flags, Qi, binom, rank0, count, corr, cum, st, s);
+    case 3: return launch_range_d<3>(M, flags, Qi, binom, rank0, count, corr, cum, st, s);
+    case 4: return launch_range_d<4>(M, flags, Qi, binom, rank0, count, corr, cum, st, s);
+    case 5: return launch_range_d<5>(M, flags, Qi, binom, rank0, count, corr, cum, st, s);
     default: return hipErrorInvalidValue;
   }
 }

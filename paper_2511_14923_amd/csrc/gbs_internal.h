@@ -62,6 +62,12 @@ hipError_t launch_forward(int d, int M, int flags, const double* Qi, const doubl
                           const double* pk, const float* E, const uint64_t* binom, double* corr,
                           double* cum, double* ptab, DeviceStatus* st, hipStream_t s);
 
+// Order-d outputs for the colex ranks rank0 .. rank0 + count - 1 only (FP64
+// tree kernel, no lower-order tables); corr / cum hold `count` values.
+hipError_t launch_forward_range(int d, int M, int flags, const double* Qi, const uint64_t* binom,
+                                uint64_t rank0, uint64_t count, double* corr, double* cum,
+                                DeviceStatus* st, hipStream_t s);
+
 // Lower-order tables read by the order-recursive kernels: p[q], m[q], k[q]
 // point at the order-q blocks (q below the order being computed).
 struct OrderTables {

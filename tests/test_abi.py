@@ -109,6 +109,14 @@ def test_invalid_arguments_rejected_on_host():
     assert C(10, 1 << 32, fake, 2, fake, 0, None) == P.GBS_E_INVALID_ARG
     assert lib.gbs_pearson(1, fake, fake, fake, 0, None) == P.GBS_E_INVALID_ARG
     assert lib.gbs_pearson(5, fake, None, fake, 0, None) == P.GBS_E_INVALID_ARG
+    # shards: ranges inside the order, FP64 only
+    Sh = lib.gbs_cumulants_shard
+    assert Sh(10, fake, 3, 0, 121, 0, None, fake, None) == P.GBS_E_INVALID_ARG  # 121 > C(10, 3)
+    assert Sh(10, fake, 3, 100, 21, 0, None, fake, None) == P.GBS_E_INVALID_ARG
+    assert Sh(10, fake, 3, -1, 5, 0, None, fake, None) == P.GBS_E_INVALID_ARG
+    assert Sh(10, fake, 3, 0, 5, 0, None, None, None) == P.GBS_E_INVALID_ARG
+    assert Sh(10, fake, 6, 0, 5, 0, None, fake, None) == P.GBS_E_INVALID_ARG
+    assert Sh(10, fake, 3, 0, 5, P.GBS_MIXED, None, fake, None) == P.GBS_E_UNSUPPORTED
 
 
 def test_status_strings():
