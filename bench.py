@@ -35,7 +35,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_forward_order5_m144.json"
 
 
 # the sources the order-5 kernel of the headline path is compiled from
-TRAFFIC_SOURCES = ("gbs_device.h", "gbs_forward_group.hip")
+TRAFFIC_SOURCES = ("gbs_device.h", "gbs_forward_group.hip", "gbs_group_tile.inc")
 
 
 def kernel_source_hash() -> str:
@@ -176,7 +176,8 @@ def batched_and_adjoint(P, torch, G, steps):
         "subsets_per_s": n_sub / wall, "kernel_ms": kms,
         "kernel_tflops": flops / (kms * 1e-3) / 1e12,
         "frac_of_fp64_peak": flops / (kms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS,
-        "kernel": "batched_kernel (all-minors tree per subset, persistent work list)"}
+        "kernel": ("persistent work lists: orders 1-2 all-minors, orders 3-4 the group "
+                   "kernel, one launch per order")}
     del bufs
     inst = G.make_instance("grad_m144_k3")
     s = torch.from_numpy(inst.sigma).to("cuda:0")
@@ -357,7 +358,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="which form gives the headline value (both are measured)")
     ap.add_argument("--only", choices=["fp64", "mixed", "fp64_all_minors", "mixed_all_minors",
-                                       "displaced", "sampler"],
+                                       "displaced", "sampler", "batched"],
                     default=None, help="measure one form only (profiling runs)")
     ap.add_argument("--all-minors", action="store_true",
                     help="also measure the all-minors kernel (GBS_ALL_MINORS) of both precisions")
@@ -396,6 +397,9 @@ def main():
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n}), flush=True)
         return
     P.lib()
+    if args.only == "batched":  # profiling runs of the batched and adjoint launches only
+        print(json.dumps(batched_and_adjoint(P, torch, G, args.steps)), flush=True)
+        return
     inst = G.make_instance("m144_k5")
     sigma = torch.from_numpy(inst.sigma).to("cuda:0")
     N = P.gbs_total_outputs(M, K)

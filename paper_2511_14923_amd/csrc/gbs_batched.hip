@@ -1,16 +1,23 @@
-// Batched forward pass: many covariance instances of uneven M in one persistent
-// launch.
+// Batched forward pass: many covariance instances of uneven M in persistent
+// launches over device work lists.
 //
-// The host builds a device work list of (instance, order, rank range) items,
-// longest first; a fixed grid of workgroups (a few per compute unit) claims
-// items with one atomic counter until the list is exhausted, so large and small
-// instances share the machine without per-instance launches or tail effects.
-// Every workgroup leaves the loop when the counter passes the end of the list:
-// no workgroup ever waits on another.
+// FP64, orders 3..K: the group kernel (gbs_forward_group.hip), one persistent
+// launch per order whose work list holds the (instance, tile) items of every
+// instance at that order; each instance reads the tables of its own lower
+// orders, which the previous launches wrote.  Orders 1 and 2, the mixed form,
+// instances the group kernel does not take (M too large) and GBS_ALL_MINORS:
+// one persistent launch over (instance, order, rank range) items, longest
+// first, each subset evaluated from all its minors (no tables needed), which
+// also stores the tables the group launches read.  In every launch a fixed grid
+// of workgroups claims items with one atomic counter until the list is
+// exhausted, so large and small instances share the machine without
+// per-instance launches or tail effects; every workgroup leaves its loop when
+// the counter passes the end of the list, and no workgroup waits on another.
 //
-// The pipeline (counter and status reset, Q of every instance, optional
-// normalisation, persistent kernel) is captured once into a HIP graph per
-// instance list and replayed; launch shapes come from the autotuner's cache.
+// The pipeline (counter and status reset, Q of every instance, diagonal blocks
+// or normalisation, the persistent launches) is captured once into a HIP graph
+// per instance list and replayed; the all-minors launch shape comes from the
+// autotuner's cache, the group launches fill the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,12 +36,15 @@ namespace gbs {
 struct BatchInstance {
   const double* sigma;
   double* Qi;
+  double* Qd;    // diagonal blocks of Q (group kernel), or null
   double* pk;
   float* E;
   double* corr;
   double* cum;
+  double* mtab;  // correlators of orders < K for the group kernel (corr, or scratch), or null
+  double* ptab;  // vacuum probabilities of orders < K for the group kernel, or null
   int M;
-  int pad;
+  int K;
   int64_t off[kMaxOrder + 2];
 };
 
@@ -47,8 +57,11 @@ struct WorkItem {
 
 namespace {
 
+// one counter per persistent launch: [0] all-minors items, [d] group items of order d
+constexpr int kCounters = kMaxOrder + 1;
+
 __global__ void reset_batch_kernel(unsigned* counter, DeviceStatus* st) {
-  *counter = 0u;
+  for (int i = 0; i < kCounters; ++i) counter[i] = 0u;
   st->flag = 0;
   st->order = 0;
   st->rank = -1;
@@ -66,6 +79,18 @@ __global__ void build_q_batched_kernel(const BatchInstance* __restrict__ inst) {
     const double v = (sr >= sc) ? I.sigma[(size_t)sr * n + sc] : I.sigma[(size_t)sc * n + sr];
     I.Qi[idx] = v + (row == col ? 0.5 : 0.0);
   }
+}
+
+__global__ void build_qdiag_batched_kernel(const BatchInstance* __restrict__ inst) {
+  const BatchInstance I = inst[blockIdx.y];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!I.Qd || k >= I.M) return;
+  const size_t ldq = 2 * (size_t)I.M;
+  const double* q = I.Qi + (size_t)(2 * k) * ldq + 2 * k;
+  I.Qd[4 * (size_t)k + 0] = q[0];
+  I.Qd[4 * (size_t)k + 1] = q[ldq];
+  I.Qd[4 * (size_t)k + 2] = q[ldq + 1];
+  I.Qd[4 * (size_t)k + 3] = 0.0;
 }
 
 __global__ void build_normalised_batched_kernel(const BatchInstance* __restrict__ inst) {
@@ -115,15 +140,18 @@ __device__ __forceinline__ void process_item(const BatchInstance& I, const WorkI
         colex_unrank<D>(r, I.M, bin, kBinLd, s);
         double mS, kS;
         bool bad = false;
+        double pS = 0.0;
         if constexpr (MIXED) {
           subset_mixed<D, CONV, true>(I.pk, I.E, I.M, s, mS, kS, bad);
         } else {
-          double pS;
           subset_fp64<D, CONV, true>(I.Qi, I.M, s, mS, kS, pS, bad);
         }
         if (bad) latch_failure(st, D, (int64_t)r);
-        if (I.corr) I.corr[I.off[D] + r] = mS;
-        I.cum[I.off[D] + r] = kS;
+        const int64_t o = I.off[D] + (int64_t)r;
+        if (I.corr) I.corr[o] = mS;
+        else if (I.mtab && D < I.K) I.mtab[o] = mS;
+        I.cum[o] = kS;
+        if (!MIXED && I.ptab && D < I.K) I.ptab[o] = pS;
       }
     }
   }
@@ -225,6 +253,15 @@ struct BatchPlan {
   int n_items = 0;
   int max_M = 0;
   int n = 0;
+  bool any_group = false;
+  // group launches, order d = 3..K
+  GroupBatchInstance* d_ginst[kMaxOrder + 1] = {};
+  GroupBatchItem* d_gitems[kMaxOrder + 1] = {};
+  uint32_t n_gitems[kMaxOrder + 1] = {};
+  int g_max_M[kMaxOrder + 1] = {};
+  int g_nwin[kMaxOrder + 1] = {};
+  size_t g_lds[kMaxOrder + 1] = {};
+  int g_grid[kMaxOrder + 1] = {};
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -254,6 +291,13 @@ bool same_key(const BatchPlan* p, int dev, int n, const gbs_instance* inst, int 
   return std::memcmp(p->key.data(), inst, sizeof(gbs_instance) * n) == 0;
 }
 
+// Order d of an instance of M modes runs on the group kernel (reading the
+// tables of its lower orders) unless the call asks for all minors or the mixed
+// form, or the group kernel does not take that (d, M).
+bool group_order(int d, int M, int flags) {
+  return d >= 3 && !(flags & (GBS_MIXED | GBS_ALL_MINORS)) && group_supported(d, M, flags, false);
+}
+
 double item_cost(const WorkItem& w) {
   // per-subset work grows like 2^d d^2 (2^d minors of a 2d x 2d matrix)
   return (double)(w.end - w.begin) * (double)(1 << w.order) * w.order * w.order;
@@ -269,6 +313,11 @@ hipError_t launch_pipeline(const BatchPlan& p, hipStream_t s, bool timed) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(build_q_batched_kernel, dim3(bx, p.n), dim3(256), 0, s, p.d_inst);
   e = hipGetLastError();
+  if (e == hipSuccess && p.any_group) {
+    hipLaunchKernelGGL(build_qdiag_batched_kernel, dim3((p.max_M + 255) / 256, p.n), dim3(256), 0,
+                       s, p.d_inst);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess && timed) e = timing_end(s);
   if (e == hipSuccess && (p.flags & GBS_MIXED)) {
     if (timed) e = timing_begin(s, GBS_STAGE_NORMALISE, 0);
@@ -282,14 +331,25 @@ hipError_t launch_pipeline(const BatchPlan& p, hipStream_t s, bool timed) {
   hipError_t ec;
   DeviceContext* ctx = current_context(&ec);
   if (!ctx) return ec;
-  const int grid = std::max(1, ctx->cu_count * p.tuning.waves_per_cu);
-  BatchedFn fn = pick_kernel(p.K, p.tuning.unroll, p.flags);
-  if (timed) e = timing_begin(s, GBS_STAGE_BATCHED, 0);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(p.tuning.block), 0, s, p.d_inst, p.d_items, p.n_items,
-                     p.d_counter, ctx->binom, p.d_status);
-  e = hipGetLastError();
-  if (e == hipSuccess && timed) e = timing_end(s);
+  if (p.n_items > 0) {
+    const int grid = std::max(1, ctx->cu_count * p.tuning.waves_per_cu);
+    BatchedFn fn = pick_kernel(p.K, p.tuning.unroll, p.flags);
+    if (timed) e = timing_begin(s, GBS_STAGE_BATCHED, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(p.tuning.block), 0, s, p.d_inst, p.d_items,
+                       p.n_items, p.d_counter, ctx->binom, p.d_status);
+    e = hipGetLastError();
+    if (e == hipSuccess && timed) e = timing_end(s);
+  }
+  for (int d = 3; d <= p.K && e == hipSuccess; ++d) {
+    if (p.n_gitems[d] == 0) continue;
+    if (timed) e = timing_begin(s, GBS_STAGE_BATCHED, d);
+    if (e == hipSuccess)
+      e = launch_group_batched(d, p.flags, p.d_ginst[d], p.d_gitems[d], p.n_gitems[d],
+                               p.d_counter + d, p.g_grid[d], p.g_max_M[d], p.g_nwin[d],
+                               p.g_lds[d], ctx->binom, p.d_status, s);
+    if (e == hipSuccess && timed) e = timing_end(s);
+  }
   return e;
 }
 
@@ -303,16 +363,47 @@ gbs_status build_plan(BatchPlan* p, int n, const gbs_instance* inst, int K, int 
   p->n = n;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) return GBS_E_DEVICE;
+  hipError_t ec;
+  DeviceContext* ctx = current_context(&ec);
+  if (!ctx) return to_status(ec);
   const bool mixed = flags & GBS_MIXED;
   std::vector<BatchInstance> host(n);
   std::vector<WorkItem> items;
+  std::vector<GroupBatchItem> gitems[kMaxOrder + 1];
   size_t bytes = 0;
   auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  std::vector<size_t> q_off(n), pk_off(n), e_off(n);
+  std::vector<size_t> q_off(n), pk_off(n), e_off(n), qd_off(n), pt_off(n), mt_off(n);
+  std::vector<bool> grp(n, false);
   p->max_M = 0;
+  p->any_group = false;
+  // group items, largest instances first
+  std::vector<int> by_M(n);
+  for (int i = 0; i < n; ++i) by_M[i] = i;
+  std::stable_sort(by_M.begin(), by_M.end(), [&](int x, int y) { return inst[x].M > inst[y].M; });
+  std::vector<uint64_t> tiles;
+  for (int d = 3; d <= K; ++d) {
+    p->g_max_M[d] = 0;
+    for (int i : by_M) {
+      if (!group_order(d, inst[i].M, flags)) continue;
+      tiles.clear();
+      group_tiles(d, inst[i].M, &tiles);
+      for (uint64_t desc : tiles) gitems[d].push_back(GroupBatchItem{(uint32_t)i, 0u, desc});
+      p->g_max_M[d] = std::max(p->g_max_M[d], inst[i].M);
+      grp[i] = true;
+    }
+  }
   for (int i = 0; i < n; ++i) {
     const int M = inst[i].M;
     p->max_M = std::max(p->max_M, M);
+    BatchInstance& b = host[i];
+    b.sigma = inst[i].sigma;
+    b.corr = inst[i].corr;
+    b.cum = inst[i].cum;
+    b.M = M;
+    b.K = K;
+    b.off[1] = 0;
+    for (int d = 1; d <= kMaxOrder; ++d)
+      b.off[d + 1] = b.off[d] + (d <= K ? (int64_t)host_binom(M, d) : 0);
     q_off[i] = bytes;
     bytes += a256(4 * (size_t)M * M * sizeof(double));
     if (mixed) {
@@ -321,16 +412,19 @@ gbs_status build_plan(BatchPlan* p, int n, const gbs_instance* inst, int K, int 
       e_off[i] = bytes;
       bytes += a256(4 * (size_t)M * M * sizeof(float));
     }
-    BatchInstance& b = host[i];
-    b.sigma = inst[i].sigma;
-    b.corr = inst[i].corr;
-    b.cum = inst[i].cum;
-    b.M = M;
-    b.pad = 0;
-    b.off[1] = 0;
-    for (int d = 1; d <= kMaxOrder; ++d)
-      b.off[d + 1] = b.off[d] + (d <= K ? (int64_t)host_binom(M, d) : 0);
+    if (grp[i]) {
+      p->any_group = true;
+      qd_off[i] = bytes;
+      bytes += a256(4 * (size_t)M * sizeof(double));
+      pt_off[i] = bytes;  // orders 1 .. K-1
+      bytes += a256((size_t)b.off[K] * sizeof(double));
+      if (!b.corr) {
+        mt_off[i] = bytes;
+        bytes += a256((size_t)b.off[K] * sizeof(double));
+      }
+    }
     for (int d = 1; d <= K; ++d) {
+      if (grp[i] && group_order(d, M, flags)) continue;
       const uint64_t cnt = host_binom(M, d);
       for (uint64_t b0 = 0; b0 < cnt; b0 += (uint64_t)t.tile)
         items.push_back(WorkItem{i, d, b0, std::min<uint64_t>(cnt, b0 + (uint64_t)t.tile)});
@@ -342,25 +436,74 @@ gbs_status build_plan(BatchPlan* p, int n, const gbs_instance* inst, int K, int 
   bytes += a256(sizeof(BatchInstance) * n);
   const size_t o_items = bytes;
   bytes += a256(sizeof(WorkItem) * items.size());
+  size_t o_ginst[kMaxOrder + 1] = {}, o_gitems[kMaxOrder + 1] = {};
+  for (int d = 3; d <= K; ++d) {
+    if (gitems[d].empty()) continue;
+    o_ginst[d] = bytes;
+    bytes += a256(sizeof(GroupBatchInstance) * n);
+    o_gitems[d] = bytes;
+    bytes += a256(sizeof(GroupBatchItem) * gitems[d].size());
+  }
   const size_t o_cnt = bytes;
-  bytes += 256;
+  bytes += a256(sizeof(unsigned) * kCounters);
   const size_t o_st = bytes;
   bytes += 256;
+  // group launch shapes (occupancy queries stay outside graph capture)
+  for (int d = 3; d <= K; ++d) {
+    p->n_gitems[d] = (uint32_t)gitems[d].size();
+    if (gitems[d].empty()) continue;
+    p->g_lds[d] = group_batched_lds(d, p->g_max_M[d], &p->g_nwin[d]);
+    e = group_batched_grid(d, flags, p->g_lds[d], ctx->cu_count, &p->g_grid[d]);
+    if (e != hipSuccess) return to_status(e);
+  }
   e = hipMalloc(&p->mem, bytes);
   if (e != hipSuccess) return to_status(e);
   char* base = static_cast<char*>(p->mem);
   for (int i = 0; i < n; ++i) {
-    host[i].Qi = reinterpret_cast<double*>(base + q_off[i]);
-    host[i].pk = mixed ? reinterpret_cast<double*>(base + pk_off[i]) : nullptr;
-    host[i].E = mixed ? reinterpret_cast<float*>(base + e_off[i]) : nullptr;
+    BatchInstance& b = host[i];
+    b.Qi = reinterpret_cast<double*>(base + q_off[i]);
+    b.pk = mixed ? reinterpret_cast<double*>(base + pk_off[i]) : nullptr;
+    b.E = mixed ? reinterpret_cast<float*>(base + e_off[i]) : nullptr;
+    b.Qd = grp[i] ? reinterpret_cast<double*>(base + qd_off[i]) : nullptr;
+    b.ptab = grp[i] ? reinterpret_cast<double*>(base + pt_off[i]) : nullptr;
+    b.mtab = !grp[i] ? nullptr : b.corr ? b.corr : reinterpret_cast<double*>(base + mt_off[i]);
   }
+  std::vector<GroupBatchInstance> gh(n);
+  for (int d = 3; d <= K && e == hipSuccess; ++d) {
+    if (gitems[d].empty()) continue;
+    for (int i = 0; i < n; ++i) {
+      const BatchInstance& b = host[i];
+      GroupBatchInstance& g = gh[i];
+      g = GroupBatchInstance{};
+      g.Qi = b.Qi;
+      g.Qd = b.Qd;
+      g.M = b.M;
+      if (!grp[i]) continue;  // never referenced by an item
+      for (int q = 1; q < d; ++q) {
+        g.tab.p[q] = b.ptab + b.off[q];
+        g.tab.m[q] = b.mtab + b.off[q];
+        g.tab.k[q] = b.cum + b.off[q];
+      }
+      g.m_out = b.corr ? b.corr + b.off[d] : (d < K ? b.mtab + b.off[d] : nullptr);
+      g.k_out = b.cum + b.off[d];
+      g.p_out = d < K ? b.ptab + b.off[d] : nullptr;
+    }
+    p->d_ginst[d] = reinterpret_cast<GroupBatchInstance*>(base + o_ginst[d]);
+    p->d_gitems[d] = reinterpret_cast<GroupBatchItem*>(base + o_gitems[d]);
+    e = hipMemcpy(p->d_ginst[d], gh.data(), sizeof(GroupBatchInstance) * n,
+                  hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_gitems[d], gitems[d].data(), sizeof(GroupBatchItem) * gitems[d].size(),
+                    hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return to_status(e);
   p->d_inst = reinterpret_cast<BatchInstance*>(base + o_inst);
   p->d_items = reinterpret_cast<WorkItem*>(base + o_items);
   p->d_counter = reinterpret_cast<unsigned*>(base + o_cnt);
   p->d_status = reinterpret_cast<DeviceStatus*>(base + o_st);
   p->n_items = (int)items.size();
   e = hipMemcpy(p->d_inst, host.data(), sizeof(BatchInstance) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess)
+  if (e == hipSuccess && !items.empty())
     e = hipMemcpy(p->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
   return to_status(e);
 }
@@ -396,7 +539,7 @@ gbs_status run_batched(int n, const gbs_instance* inst, int K, int flags, void* 
   hipError_t e;
   DeviceContext* ctx = current_context(&e);
   if (!ctx) return to_status(e);
-  const int key_flags = flags & (GBS_PARITY | GBS_MIXED);
+  const int key_flags = flags & (GBS_PARITY | GBS_MIXED | GBS_ALL_MINORS);
   const gbs_tuning t = lookup_tuning(ctx->device, K, flags);
   BatchPlan* plan = nullptr;
   {
@@ -459,7 +602,8 @@ gbs_status run_autotune(int n, const gbs_instance* inst, int K, int flags, void*
   gbs_status result = GBS_OK;
   for (const gbs_tuning& t : cands) {
     BatchPlan plan;
-    gbs_status st = build_plan(&plan, n, inst, K, flags & (GBS_PARITY | GBS_MIXED), t);
+    gbs_status st =
+        build_plan(&plan, n, inst, K, flags & (GBS_PARITY | GBS_MIXED | GBS_ALL_MINORS), t);
     if (st != GBS_OK) {
       plan.release();
       result = st;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "gbs_device.h"
 
 namespace gbs {
@@ -93,6 +95,36 @@ hipError_t launch_forward_group(int d, int M, int flags, const double* Qi, const
                                 const double* mi, const uint64_t* binom, const OrderTables& tab,
                                 double* m_out, double* k_out, double* p_out, DeviceStatus* st,
                                 hipStream_t s);
+
+// The group kernel over many zero-mean instances: one persistent launch per
+// order claims (instance, tile) items from a device work list.  Instance i of
+// order d reads its lower-order tables through tab and writes the order-d
+// blocks m_out (may be null), k_out and p_out (may be null).
+struct GroupBatchInstance {
+  const double* Qi;
+  const double* Qd;
+  OrderTables tab;
+  double* m_out;
+  double* k_out;
+  double* p_out;
+  int M;
+  int pad;
+};
+struct GroupBatchItem {
+  uint32_t inst;
+  uint32_t pad;
+  uint64_t desc;  // tile descriptor of the instance's plan
+};
+// Tile descriptors of order d for M modes, appended to out (host).
+void group_tiles(int d, int M, std::vector<uint64_t>* out);
+// LDS bytes and bitmap windows of a batched launch of order d whose largest M is max_M.
+size_t group_batched_lds(int d, int max_M, int* nwin_max);
+// Workgroups that fit on the device at once for that LDS size (before capture).
+hipError_t group_batched_grid(int d, int flags, size_t lds, int cu_count, int* grid);
+hipError_t launch_group_batched(int d, int flags, const GroupBatchInstance* inst,
+                                const GroupBatchItem* items, uint32_t n_items, unsigned* counter,
+                                int grid, int max_M, int nwin_max, size_t lds,
+                                const uint64_t* binom, DeviceStatus* st, hipStream_t s);
 
 // Order-recursive FP64 forward pass of order d (see gbs_forward_rec.hip):
 // p_tab/m_tab/k_tab[q] point at the order-q blocks of the lower-order tables

@@ -40,7 +40,11 @@ def _alloc(batch, K, want_corr=True):
 
 
 def _singles(P, bufs, K, flags):
-    """Single-instance calls with the batched launch's all-minors kernel."""
+    """Single-instance calls of the same arithmetic: the default kernels for
+    FP64 (the batched launch runs the group kernel at orders >= 3), the
+    all-minors kernel for the mixed form and for GBS_ALL_MINORS."""
+    if not (flags & (P.GBS_MIXED | P.GBS_ALL_MINORS)):
+        return [P.gbs_cumulants(M, s, K, flags) for (M, s, _, _) in bufs]
     return [P.gbs_cumulants(M, s, K, flags | P.GBS_ALL_MINORS) for (M, s, _, _) in bufs]
 
 
@@ -54,7 +58,7 @@ def _agree(a, b, mixed=False):
     return bool(torch.allclose(a, b, rtol=1e-12, atol=1e-13))
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2], ids=["fp64", "parity", "mixed"])
+@pytest.mark.parametrize("flags", [0, 1, 2, 16], ids=["fp64", "parity", "mixed", "all_minors"])
 def test_batch48_equals_single_calls(P, flags):
     """The 48-instance M ~ U{40..144}, K = 4 workload: every instance's output
     agrees with a separate gbs_cumulants call of the same kernel."""
@@ -166,3 +170,54 @@ def test_batched_timing_entries(P):
     for (M, s, corr, cum) in bufs:
         c1, k1 = P.gbs_cumulants(M, s, 3, P.GBS_ALL_MINORS)
         assert _agree(corr, c1) and _agree(cum, k1)
+
+
+def test_order5_tables_scratch_and_fallback(P, c_oracle):
+    """K = 5 over instances of uneven M, some without correlator outputs (the
+    group kernel then keeps the lower-order correlators in plan scratch), and
+    one of M = 150, whose order 5 (more than 2^29 subsets) falls back to the
+    all-minors launch while orders 3 and 4 run on the group kernel; sampled
+    outputs of every order against the C oracle."""
+    import torch
+    _say("case: batch K=5 scratch + fallback")
+    Ms = [150, 23, 9, 31, 5]
+    batch = [G.make_instance("m144_k5", M=m, seed=300 + m) for m in Ms]
+    bufs = []
+    for j, inst in enumerate(batch):
+        s = torch.from_numpy(inst.sigma).to("cuda:0")
+        n = O.total_outputs(inst.M, 5)
+        corr = torch.empty(n, dtype=torch.float64, device="cuda:0") if j % 2 == 0 else None
+        bufs.append((inst.M, s, corr, torch.empty(n, dtype=torch.float64, device="cuda:0")))
+    P.gbs_cumulants_batched(bufs, 5, 0)
+    torch.cuda.synchronize()
+    for i, (inst, (M, _, corr, cum)) in enumerate(zip(batch, bufs)):
+        for d in range(1, 6):
+            n = math.comb(M, d)
+            ranks = G.random_ranks(n, 300 if M > 100 else 2000, seed=700 * i + d)
+            rc, rk = O.c_forward_sample(inst.sigma, d, ranks)
+            vmu, vkap = O.c_error_floor(inst.sigma, d, ranks)
+            idx = torch.from_numpy(O.order_offset(M, d) + ranks.astype(np.int64)).to("cuda:0")
+            if corr is not None:
+                got = corr[idx].cpu().numpy()
+                assert_within(got, rc, fp64_tolerance(rc, vmu), f"M={M} corr d={d}")
+            got = cum[idx].cpu().numpy()
+            assert_within(got, rk, fp64_tolerance(rk, vkap), f"M={M} cum d={d}")
+    # the small instances also agree with single calls everywhere
+    for (M, s, corr, cum) in bufs[1:]:
+        c1, k1 = P.gbs_cumulants(M, s, 5, 0)
+        assert _agree(cum, k1), M
+        if corr is not None:
+            assert _agree(corr, c1), M
+
+
+def test_group_launches_in_timing(P):
+    """FP64 at K = 4: one all-minors launch (orders 1, 2) and one group launch
+    per order 3, 4 appear as 'batched' stages."""
+    import torch
+    _say("case: batched group timing")
+    batch = G.make_batch(count=4, seed=19, m_range=(12, 40))
+    bufs = _alloc(batch, 4)
+    P.gbs_cumulants_batched(bufs, 4, P.GBS_TIMING)
+    torch.cuda.synchronize()
+    orders = sorted(o for st, o, _ in P.gbs_last_timings() if st == "batched")
+    assert orders == [0, 3, 4], orders
