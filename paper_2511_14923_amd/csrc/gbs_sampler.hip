@@ -161,14 +161,15 @@ __global__ __launch_bounds__(64 * kSampWaves) void sampler_kernel(
     for (int i = 2; i < n; ++i) {
       const uint32_t xi = x.get(i);
       const int j0 = 1 + (w + kSampWaves - (int)(c2((uint32_t)i - 1) % kSampWaves)) % kSampWaves;
+      if (j0 >= i) continue;
+      const double A = t.pp(n - 1, i + 1);  // the same for every j of this i
       for (int j = j0; j < i; j += kSampWaves) {
         const uint32_t sij = xi ^ x.get(j);
         if constexpr (K == 3) {
-          D += flip(0.125 * kap[o3 + r2(i) + r1(j)] * t.pp(n - 1, i + 1) * t.p1(i - 1, j), sij);
+          D += flip(0.125 * kap[o3 + r2(i) + r1(j)] * A * t.p1(i - 1, j), sij);
         } else {
           const uint32_t o4 = ko.off[4] + r4(n);
           double v = 0.125 * kap[o3 + r2(i) + r1(j)] * t.p2(n - 1, i, j);
-          const double A = t.pp(n - 1, i + 1);
           double a4 = 0.0;
           const uint32_t ok4 = o4 + r3(i) + r2(j);
 #pragma unroll 4
@@ -241,12 +242,13 @@ __global__ __launch_bounds__(64 * kSampWaves) void sampler_kernel(
     const double h = 0.5 + flip(0.5 * kap[ko.off[1] + r1(n)], xn);
     if constexpr (K == 3) {
       for (int e = 1 + w; e < n; e += kSampWaves) {
-        double v = h * t.p1(n - 1, e);
-        for (int i = 1; i < n; ++i) {
-          if (i == e) continue;
-          const int lo = i < e ? i : e, hi = i < e ? e : i;
-          v += flip(0.25 * kap[o2 + r1(i)] * t.pp(n - 1, hi + 1) * t.p1(hi - 1, lo), x.get(i) ^ xn);
-        }
+        // terms i < e share the factor p+(n-1..e+1); terms i > e carry p+(n-1..i+1)
+        double below = 0.0, above = 0.0;
+        for (int i = 1; i < e; ++i)
+          below += flip(kap[o2 + r1(i)] * t.p1(e - 1, i), x.get(i) ^ xn);
+        for (int i = e + 1; i < n; ++i)
+          above += flip(kap[o2 + r1(i)] * t.pp(n - 1, i + 1) * t.p1(i - 1, e), x.get(i) ^ xn);
+        const double v = h * t.p1(n - 1, e) + 0.25 * fma(t.pp(n - 1, e + 1), below, above);
         t.put(t.P1, c2((uint32_t)n - 1) + (uint32_t)e - 1, v);
       }
       for (int l = 1 + w; l <= n; l += kSampWaves) {
@@ -258,50 +260,64 @@ __global__ __launch_bounds__(64 * kSampWaves) void sampler_kernel(
     } else {
       for (int l = 1 + w; l <= n; l += kSampWaves) {
         double v = h * t.pp(n - 1, l);
-        for (int i = l; i < n; ++i)
-          v += flip(0.25 * kap[o2 + r1(i)] * t.pp(n - 1, i + 1) * t.pp(i - 1, l), x.get(i) ^ xn);
-        for (int i = l + 1; i < n; ++i) {
-          const double Ai = t.pp(n - 1, i + 1);
-          double ai = 0.0;
+        for (int i = l; i < n; ++i) {
+          const double Ai = t.pp(n - 1, i + 1);  // shared by the order-3 and order-4 terms of i
+          double ai = 0.25 * kap[o2 + r1(i)] * t.pp(i - 1, l);
+          double a3 = 0.0;
           for (int j = l; j < i; ++j)
-            ai += flip(kap[o3 + r2(i) + r1(j)] * t.pp(i - 1, j + 1) * t.pp(j - 1, l), x.get(j));
-          v += flip(0.125 * Ai * ai, x.get(i) ^ xn);
+            a3 += flip(kap[o3 + r2(i) + r1(j)] * t.pp(i - 1, j + 1) * t.pp(j - 1, l), x.get(j));
+          ai = fma(0.125, a3, ai);
+          v += flip(Ai * ai, x.get(i) ^ xn);
         }
         t.put(t.PP, c2((uint32_t)n) + (uint32_t)l - 1, v);
       }
       for (int e = 1 + w; e < n; e += kSampWaves) {
-        double v = h * t.p1(n - 1, e);
-        for (int i = 1; i < n; ++i) {
-          if (i == e) continue;
-          const int hi = i > e ? i : e, lo = i > e ? e : i;
-          v += flip(0.25 * kap[o2 + r1(i)] * t.p2(n - 1, hi, lo), x.get(i) ^ xn);
-        }
+        // Loops are split where the order of the elided bits changes, so
+        // that each runs over consecutive table entries without a branch.
+        double v3 = 0.0;
+#pragma unroll 2
+        for (int i = 1; i < e; ++i)
+          v3 += flip(kap[o2 + r1(i)] * t.p2(n - 1, e, i), x.get(i) ^ xn);
+#pragma unroll 2
+        for (int i = e + 1; i < n; ++i)
+          v3 += flip(kap[o2 + r1(i)] * t.p2(n - 1, i, e), x.get(i) ^ xn);
+        double v = fma(0.25, v3, h * t.p1(n - 1, e));
         for (int i = 2; i < n; ++i) {
           if (i == e) continue;
+          // (a, b, c): i, j, e in decreasing order; a = max(i, e) does not depend on j
+          const int a = e > i ? e : i;
+          const double A = t.pp(n - 1, a + 1);
+          const uint32_t ki = o3 + r2(i);
           double ai = 0.0;
-          for (int j = 1; j < i; ++j) {
-            if (j == e) continue;
-            // (a, b, c): i, j, e in decreasing order
-            const int a = e > i ? e : i;
-            const int b = e > i ? i : (e > j ? e : j);
-            const int c = e > j ? j : e;
-            ai += flip(kap[o3 + r2(i) + r1(j)] * t.pp(n - 1, a + 1) * t.p2(a - 1, b, c), x.get(j));
+          if (i < e) {
+#pragma unroll 2
+            for (int j = 1; j < i; ++j) ai += flip(kap[ki + r1(j)] * t.p2(e - 1, i, j), x.get(j));
+          } else {
+#pragma unroll 2
+            for (int j = 1; j < e; ++j) ai += flip(kap[ki + r1(j)] * t.p2(i - 1, e, j), x.get(j));
+#pragma unroll 2
+            for (int j = e + 1; j < i; ++j) ai += flip(kap[ki + r1(j)] * t.p2(i - 1, j, e), x.get(j));
           }
-          v += flip(0.125 * ai, x.get(i) ^ xn);
+          v += flip(0.125 * A * ai, x.get(i) ^ xn);
         }
         t.put(t.P1, c2((uint32_t)n - 1) + (uint32_t)e - 1, v);
       }
       for (int e = 2; e < n; ++e) {
         const int d0 = 1 + (w + kSampWaves - (int)(c2((uint32_t)e - 1) % kSampWaves)) % kSampWaves;
         for (int d = d0; d < e; d += kSampWaves) {
-          double v = h * t.p2(n - 1, e, d);
-          for (int i = 1; i < n; ++i) {
-            if (i == e || i == d) continue;
-            const int a = i > e ? i : e;
-            const int b = i > e ? e : (i > d ? i : d);
-            const int c = i > d ? d : i;
-            v += flip(0.25 * kap[o2 + r1(i)] * t.pp(n - 1, a + 1) * t.p2(a - 1, b, c), x.get(i) ^ xn);
-          }
+          // (a, b, c): i, e, d in decreasing order.  Terms i < e have a = e and
+          // share the factor p+(n-1..e+1); terms i > e have (a, b, c) = (i, e, d).
+          double below = 0.0, above = 0.0;
+#pragma unroll 2
+          for (int i = 1; i < d; ++i)
+            below += flip(kap[o2 + r1(i)] * t.p2(e - 1, d, i), x.get(i) ^ xn);
+#pragma unroll 2
+          for (int i = d + 1; i < e; ++i)
+            below += flip(kap[o2 + r1(i)] * t.p2(e - 1, i, d), x.get(i) ^ xn);
+#pragma unroll 2
+          for (int i = e + 1; i < n; ++i)
+            above += flip(kap[o2 + r1(i)] * t.pp(n - 1, i + 1) * t.p2(i - 1, e, d), x.get(i) ^ xn);
+          const double v = h * t.p2(n - 1, e, d) + 0.25 * fma(t.pp(n - 1, e + 1), below, above);
           t.put(t.P2, c3((uint32_t)n - 1) + c2((uint32_t)e - 1) + (uint32_t)d - 1, v);
         }
       }
