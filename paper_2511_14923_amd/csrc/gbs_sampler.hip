@@ -24,9 +24,10 @@
 // and splits every step's sums between its waves (single indices and index
 // pairs dealt round-robin, so that the waves get near-equal work), reducing the
 // partial D_n through LDS.  The tables of all tops live in
-// HBM, entry-major with the samples of a launch interleaved (entry t of sample
-// s at t * ld + s), so every table access of a wavefront is one contiguous
-// 512-byte read.  Cumulant indices depend only on loop counters and are the
+// HBM, one contiguous block per workgroup, entry-major with the workgroup's 64
+// samples interleaved (entry t of lane l at t * 64 + l): every table access of
+// a wavefront is one contiguous 512-byte read, and the runs of consecutive
+// entries that the sums walk are consecutive in memory.  Cumulant indices depend only on loop counters and are the
 // same for every lane: they are scalar loads.  Each workgroup's samples are
 // independent of every other workgroup's, so one launch runs all M steps with
 // workgroup barriers between the phases of a step.
@@ -130,7 +131,7 @@ __device__ __forceinline__ uint32_t r5(int x) {
 template <int K, int kSampWaves = samp_waves<K>()>
 __global__ __launch_bounds__(64 * kSampWaves) void sampler_kernel(
     const double* __restrict__ kap, KapOffsets ko, int M, const double* __restrict__ u,
-    uint64_t ldu, int64_t nsamp, double* __restrict__ tab, uint64_t ldt, SampLayout L,
+    uint64_t ldu, int64_t nsamp, double* __restrict__ tab, SampLayout L,
     uint8_t* __restrict__ bits_out, double* __restrict__ prob, double* __restrict__ cond) {
   __shared__ double red[kSampWaves][64];
   const int lane = threadIdx.x & 63;
@@ -138,12 +139,12 @@ __global__ __launch_bounds__(64 * kSampWaves) void sampler_kernel(
   const int64_t s = (int64_t)blockIdx.x * 64 + lane;
   const bool live = s < nsamp;
   Tables t;
-  t.ld = ldt;
-  t.s = (uint32_t)s;  // < ldt: dead lanes of the last workgroup work on spare columns
-  t.P0 = tab;
-  t.P1 = tab + (uint64_t)L.n0 * ldt;
-  t.PP = t.P1 + (uint64_t)L.n1 * ldt;
-  t.P2 = t.PP + (uint64_t)L.npp * ldt;
+  t.ld = 64;
+  t.s = (uint32_t)lane;  // dead lanes of the last workgroup work on their own columns
+  t.P0 = tab + (uint64_t)blockIdx.x * L.entries() * 64;
+  t.P1 = t.P0 + (uint64_t)L.n0 * 64;
+  t.PP = t.P1 + (uint64_t)L.n1 * 64;
+  t.P2 = t.PP + (uint64_t)L.npp * 64;
   if (w == 0) t.put(t.P0, 0, 1.0);
   Bits x;
   __syncthreads();
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(64 * kSampWaves) void sampler_kernel(
           for (int k = 2; k < j; ++k) {
             double ak = 0.0;
             const uint32_t rk = r2(k);
-#pragma unroll 2
+#pragma unroll 4
             for (int l = 1; l < k; ++l) {
               double kw = 0.0;
 #pragma unroll
@@ -353,7 +354,7 @@ hipError_t run_sampler(int M, int K, const double* kap, int64_t nsamples, const 
   // equal launches: a small last launch would run for as long as a full one
   const int64_t nlaunch = (nsamples + batch - 1) / batch;
   batch = ((nsamples + nlaunch - 1) / nlaunch + 63) / 64 * 64;
-  const uint64_t ldt = (uint64_t)(batch + 63) / 64 * 64;
+  const uint64_t ldt = (uint64_t)(batch + 63) / 64 * 64;  // table columns: 64 per workgroup
   void* scratch = nullptr;
   hipError_t e = hipMallocAsync(&scratch, (size_t)L.entries() * ldt * sizeof(double), s);
   if (e != hipSuccess) return e;
@@ -363,11 +364,11 @@ hipError_t run_sampler(int M, int K, const double* kap, int64_t nsamples, const 
     const unsigned grid = (unsigned)((nb + 63) / 64);
     if (K == 3)
       hipLaunchKernelGGL(sampler_kernel<3>, dim3(grid), dim3(64 * samp_waves<3>()), 0, s, kap, ko, M,
-                         u + s0, (uint64_t)nsamples, nb, tab, ldt, L, bits + s0 * M,
+                         u + s0, (uint64_t)nsamples, nb, tab, L, bits + s0 * M,
                          prob ? prob + s0 : nullptr, cond ? cond + s0 : nullptr);
     else
       hipLaunchKernelGGL(sampler_kernel<5>, dim3(grid), dim3(64 * samp_waves<5>()), 0, s, kap, ko, M,
-                         u + s0, (uint64_t)nsamples, nb, tab, ldt, L, bits + s0 * M,
+                         u + s0, (uint64_t)nsamples, nb, tab, L, bits + s0 * M,
                          prob ? prob + s0 : nullptr, cond ? cond + s0 : nullptr);
     e = hipGetLastError();
   }
