@@ -32,20 +32,22 @@ PEAK_VALU_TFLOPS = 78.6  # one non-packed FMA per lane per clock: 256 CU x 64 la
 WORKLOAD = ("m144_k5: M=144 modes, subsets of order 1..5 (498,685,188), Haar interferometer, "
             "x-squeezing r~U[0.6,1.6], input loss eta~U[0.25,0.4], xxpp, hbar=1")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_forward_order5_m144.json")
+SAMPLER_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sampler_m144.json")
+PEAK_HBM_BYTES = 8e12
 
 
 # the sources the order-5 kernel of the headline path is compiled from
 TRAFFIC_SOURCES = ("gbs_device.h", "gbs_forward_group.hip", "gbs_group_tile.inc")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the order-5 kernel's sources with comments and whitespace
-    removed, so that the stored counter readings stay valid across comment-only
-    edits and edits of other kernels."""
+def kernel_source_hash(sources=TRAFFIC_SOURCES) -> str:
+    """Hash of a kernel's sources (default: the order-5 kernel's) with comments
+    and whitespace removed, so that the stored counter readings stay valid
+    across comment-only edits and edits of other kernels."""
     import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_14923_amd", "csrc")
-    for name in TRAFFIC_SOURCES:
+    for name in sources:
         with open(os.path.join(csrc, name), encoding="utf-8") as f:
             text = f.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
@@ -222,6 +224,21 @@ def sampler_terms(M_, K_):
     return tot
 
 
+def sampler_traffic(K_):
+    """HBM bytes per sample of the sampler kernel from the committed rocprofv3
+    counter runs (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration),
+    or None when missing or taken on different kernel sources."""
+    try:
+        with open(SAMPLER_TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(f"k{K_}")
+    if not ent or rec.get("source_hash") != kernel_source_hash(("gbs_sampler.hip",)):
+        return None
+    return ent.get("bytes_per_sample")
+
+
 def sampler_legs(P, torch, np, G, sigma, counts):
     """Stage 2 on the stage-1 output: parity cumulants of the M = 144 workload
     (gbs_cumulants, GBS_PARITY) -> gbs_sample, single elision (K = 3) and
@@ -244,11 +261,17 @@ def sampler_legs(P, torch, np, G, sigma, counts):
         terms = sampler_terms(M, K_) * n
         if K_ == 3:
             keep = bits
+        per = sampler_traffic(K_)
+        hbm = None
+        if per is not None:  # the per-sample tables stream from HBM: bytes grow with n
+            rate = per * n / (kms * 1e-3)
+            hbm = {"bound": "hbm", "bytes": per * n, "achieved_gb_per_s": rate / 1e9,
+                   "peak_gb_per_s": PEAK_HBM_BYTES / 1e9, "frac": rate / PEAK_HBM_BYTES,
+                   "source": os.path.relpath(SAMPLER_TRAFFIC_FILE, ROOT)}
         out[f"sample_k{K_}_m144"] = {
             "samples": n, "seconds": wall, "samples_per_s": n / wall, "kernel_ms": kms,
             "terms_per_sample": sampler_terms(M, K_), "terms_per_s": terms / (kms * 1e-3),
-            "table_read_gb_per_s": 8.0 * terms / (kms * 1e-3) / 1e9,
-            "frac_of_hbm_peak": 8.0 * terms / (kms * 1e-3) / 8e12,
+            "roofline": hbm,
             "mean_clicks": float(bits.float().mean().item() * M),
             "method": "single elision" if K_ == 3 else "double elision"}
         del kap, u, bits, prob
