@@ -63,7 +63,10 @@ def log(*a):
 
 def run_precision(P, torch, sigma, corr, cum, flags, steps, warmup, label, mu=None):
     """Time `steps` calls of gbs_cumulants (or, with a mean vector mu,
-    gbs_cumulants_displaced) on resident buffers."""
+    gbs_cumulants_displaced) on resident buffers: back to back (GBS_ASYNC)
+    between two device synchronisations, then the status of the last call;
+    then `steps` more calls with a HIP event pair around every launch
+    (GBS_TIMING) for the per-order kernel durations."""
     def call(fl):
         if mu is None:
             P.gbs_cumulants(M, sigma, K, fl, corr=corr, cum=cum)
@@ -74,16 +77,21 @@ def run_precision(P, torch, sigma, corr, cum, flags, steps, warmup, label, mu=No
         call(flags)
         log(f"[bench] {label} warmup {i + 1}/{warmup} done")
     torch.cuda.synchronize()
-    kern = {d: [] for d in range(1, K + 1)}
     t0 = time.perf_counter()
+    for i in range(steps):
+        call(flags | P.GBS_ASYNC)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    st, order, rank = P.gbs_last_error()
+    if st != P.GBS_OK:
+        raise P.GBSError(st, f"{label}: failing subset at order {order}, rank {rank}")
+    log(f"[bench] {label}: {steps} steps in {t:.3f} s")
+    kern = {d: [] for d in range(1, K + 1)}
     for i in range(steps):
         call(flags | P.GBS_TIMING)
         for stage, order, ms in P.gbs_last_timings():
             if stage == "forward":
                 kern[order].append(ms)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    log(f"[bench] {label}: {steps} steps in {t:.3f} s")
     ms_step = 1e3 * t / steps
     n = sum(math.comb(M, d) for d in range(1, K + 1))
     k5 = sum(kern[5]) / len(kern[5])
