@@ -100,6 +100,7 @@ def run_precision(P, torch, sigma, corr, cum, flags, steps, warmup, label, mu=No
         "ms_per_step": ms_step,
         "subsets_per_s": n / (ms_step * 1e-3),
         "kernel_ms": {d: sum(v) / len(v) for d, v in kern.items()},
+        "kernel_ms_median": {d: sorted(v)[len(v) // 2] for d, v in kern.items()},
         "order5_kernel_ms": k5,
         "order5_tflops": flops5 / (k5 * 1e-3) / 1e12,
     }
