@@ -390,7 +390,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="which form gives the headline value (both are measured)")
     ap.add_argument("--only", choices=["fp64", "mixed", "fp64_all_minors", "mixed_all_minors",
-                                       "displaced", "sampler", "batched"],
+                                       "displaced", "sampler", "batched", "shard"],
                     default=None, help="measure one form only (profiling runs)")
     ap.add_argument("--all-minors", action="store_true",
                     help="also measure the all-minors kernel (GBS_ALL_MINORS) of both precisions")
@@ -431,6 +431,9 @@ def main():
     P.lib()
     if args.only == "batched":  # profiling runs of the batched and adjoint launches only
         print(json.dumps(batched_and_adjoint(P, torch, G, args.steps)), flush=True)
+        return
+    if args.only == "shard":  # profiling runs of the M = 1152 shard only
+        print(json.dumps(shard_leg(P, torch, G, G.make_instance("m144_k5"))), flush=True)
         return
     inst = G.make_instance("m144_k5")
     sigma = torch.from_numpy(inst.sigma).to("cuda:0")
