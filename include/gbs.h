@@ -199,21 +199,28 @@ typedef struct {
     double* cum;         /* device, N(M, K) FP64 (required)                                   */
 } gbs_instance;
 
-/* Many instances of uneven M in one persistent launch (plus one launch that
- * forms every instance's Q).  Work items are independent, so every subset is
- * evaluated by the all-minors arithmetic: results agree with n separate
- * gbs_cumulants calls to FP64 rounding (the same arithmetic compiled into a
- * different kernel may round its last bits differently).  The pipeline is captured once into a HIP
- * graph per (stream, instance list, order, flags) and replayed on later calls
- * with the same list; block shape and unroll come from gbs_autotune_batched's
- * cached choice when one exists for this device, else from a fixed default.
+/* Many instances of uneven M in persistent launches over device work lists
+ * (plus the launches that form every instance's Q): one launch over
+ * (instance, order, rank range) items evaluated from all the principal minors
+ * of Q_S (orders 1 and 2; every order with GBS_MIXED or GBS_ALL_MINORS, and
+ * for instances the group kernel does not take), then, in FP64, one launch per
+ * order 3..max_order over the (instance, tile) items of the group kernel, which
+ * reads each instance's lower-order tables.  Results agree with n separate
+ * gbs_cumulants calls (same flags) to FP64 rounding.  Library-owned scratch
+ * per instance list: Q and its diagonal blocks, and, for the group launches,
+ * the vacuum probabilities of orders 1..max_order-1 (and their correlators when
+ * inst.corr is NULL).  The pipeline is captured once into a HIP graph per
+ * (instance list, order, flags, tuning) and replayed on later calls with the
+ * same list; the all-minors launch takes its block shape and unroll from
+ * gbs_autotune_batched's cached choice when one exists for this device, else
+ * from a fixed default; the group launches fill the device.
  *   n      1 <= n <= 4096
  *   inst   HOST array of n descriptors (pointers inside are device pointers)
  */
 GBS_API gbs_status gbs_cumulants_batched(int32_t n, const gbs_instance* inst, int32_t max_order,
                                  int32_t flags, void* stream);
 
-/* Launch shape of the batched kernel. */
+/* Launch shape of the batched all-minors launch. */
 typedef struct {
     int32_t block;   /* threads per workgroup: 64, 128 or 256               */
     int32_t unroll;  /* subsets per thread and work item: 1, 2 or 4         */
