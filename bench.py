@@ -347,10 +347,18 @@ def shard_leg(P, torch, G, inst):
     kms = sum(ms for st, order, ms in P.gbs_last_timings() if st == "forward")
     rate = cnt / (kms * 1e-3)
     log(f"[bench] shard M=1152 order 5: {cnt} subsets in {kms:.1f} ms")
+    # the same shard by the all-minors kernel, for comparison
+    P.gbs_cumulants_shard(M_, sig, 5, r0, cnt, P.GBS_TIMING | P.GBS_ALL_MINORS, corr=corr, cum=cum)
+    torch.cuda.synchronize()
+    kms_am = sum(ms for st, order, ms in P.gbs_last_timings() if st == "forward")
+    flops = cnt * FLOPS_PER_SUBSET[5]
     return {"M": M_, "order": 5, "rank0": r0, "subsets": cnt, "seconds": wall, "kernel_ms": kms,
             "subsets_per_s": rate, "order5_total": total,
             "full_order5_one_gpu_s": total / rate, "full_order5_eight_gpus_s": total / rate / 8,
-            "kernel": "tree kernel (all 31 minors per subset), one shard of the colex rank range"}
+            "frac_of_fp64_peak": flops / (kms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS,
+            "all_minors_kernel_ms": kms_am,
+            "kernel": "B-tiled kernel (the minors of Q_B shared by the subsets {a} + B), "
+                      "one shard of the colex rank range"}
 
 
 def cpu_baseline(np, O, G, inst, seconds):

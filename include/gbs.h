@@ -159,16 +159,19 @@ GBS_API gbs_status gbs_cumulants_displaced(int32_t M, const double* sigma, const
 
 /* One shard of one order: the correlators and cumulants of the order-`order`
  * subsets with colex ranks rank0 .. rank0 + count - 1 (in rank order), each
- * evaluated from Q alone by the all-minors kernel (every principal minor of
- * Q_S, no lower-order tables), so that disjoint rank ranges are independent
- * work: the unit by which the computation splits across devices for large M
- * (e.g. M = 1152 pseudo-photon-number-resolving detection, C(1152, 5) = 1.7e13
- * order-5 subsets).  Same definitions and tolerance as gbs_cumulants.
+ * evaluated from Q alone (no lower-order tables), so that disjoint rank ranges
+ * are independent work: the unit by which the computation splits across
+ * devices for large M (e.g. M = 1152 pseudo-photon-number-resolving detection,
+ * C(1152, 5) = 1.7e13 order-5 subsets).  Orders 3..5 run the B-tiled kernel
+ * (the subsets {a} + B of one B share the principal minors of Q_B); orders 1,
+ * 2 and GBS_ALL_MINORS run the all-minors kernel of gbs_cumulants'
+ * GBS_ALL_MINORS, whose shards are bit-identical to slices of that full pass.
+ * Same definitions and tolerance as gbs_cumulants.
  *   order        1 <= order <= min(GBS_MAX_ORDER, M)
  *   rank0, count rank0 >= 0, count >= 0, rank0 + count <= C(M, order)
  *   corr, cum    device, count FP64 each (either may be NULL, not both)
- *   flags        GBS_CLICK/GBS_PARITY | GBS_ASYNC | GBS_TIMING (GBS_MIXED and
- *                GBS_ALL_MINORS give GBS_E_UNSUPPORTED)
+ *   flags        GBS_CLICK/GBS_PARITY | GBS_ASYNC | GBS_TIMING | GBS_ALL_MINORS
+ *                (GBS_MIXED gives GBS_E_UNSUPPORTED)
  * Other arguments and errors as gbs_cumulants; gbs_last_error reports the
  * global colex rank of a failing subset. */
 GBS_API gbs_status gbs_cumulants_shard(int32_t M, const double* sigma, int32_t order, int64_t rank0,

@@ -298,7 +298,11 @@ gbs_status run_shard(int32_t M, const double* sigma, int32_t d, int64_t rank0, i
   if (e == hipSuccess) e = launch_build_q(sigma, M, Qi, s);
   if (e == hipSuccess) e = timing_end(s);
   if (e == hipSuccess) e = timing_begin(s, GBS_STAGE_FORWARD, d);
-  if (e == hipSuccess)
+  // orders >= 3: the B-tiled kernel; orders 1, 2 and GBS_ALL_MINORS: the all-minors kernel
+  if (e == hipSuccess && d >= 3 && !(flags & GBS_ALL_MINORS))
+    e = launch_forward_shard(d, M, flags, Qi, ctx->binom, (uint64_t)rank0, (uint64_t)count, corr,
+                             cum, st, s);
+  else if (e == hipSuccess)
     e = launch_forward_range(d, M, flags, Qi, ctx->binom, (uint64_t)rank0, (uint64_t)count, corr,
                              cum, st, s);
   if (e == hipSuccess) e = timing_end(s);
@@ -454,7 +458,7 @@ gbs_status gbs_cumulants_shard(int32_t M, const double* sigma, int32_t order, in
   if (!valid_problem(M, order, flags) || !sigma || (!corr && !cum)) return GBS_E_INVALID_ARG;
   if (rank0 < 0 || count < 0) return GBS_E_INVALID_ARG;
   if ((uint64_t)rank0 + (uint64_t)count > host_binom(M, order)) return GBS_E_INVALID_ARG;
-  if (flags & (GBS_MIXED | GBS_ALL_MINORS)) return GBS_E_UNSUPPORTED;
+  if (flags & GBS_MIXED) return GBS_E_UNSUPPORTED;
   return run_shard(M, sigma, order, rank0, count, flags, corr, cum, stream);
 }
 

@@ -35,23 +35,63 @@ def _dev(x):
 
 @pytest.mark.parametrize("conv", [0, 1], ids=["click", "parity"])
 def test_shard_is_a_slice_of_the_full_pass(P, conv):
+    """Ranges at the start, inside and at the end of order 5 (partial B runs at
+    both ends): with GBS_ALL_MINORS the shard runs the all-minors kernel of the
+    full pass and its outputs are the same bits; the default B-tiled kernel
+    agrees with the full pass to FP64 rounding and with the oracle."""
     import torch
     _say("case: shard slice M=40", conv)
     inst = G.make_instance("m144_k5", M=40, seed=71)
     s = _dev(inst.sigma)
     c_all, k_all = P.gbs_cumulants(40, s, 5, conv | P.GBS_ALL_MINORS)
+    c_def, k_def = P.gbs_cumulants(40, s, 5, conv)
     off = P.gbs_order_offset(40, 5)
     for r0, cnt in ((0, 1), (0, 70_001), (123_457, 99_999), (math.comb(40, 5) - 513, 513)):
-        c, k = P.gbs_cumulants_shard(40, s, 5, r0, cnt, conv)
+        c, k = P.gbs_cumulants_shard(40, s, 5, r0, cnt, conv | P.GBS_ALL_MINORS)
         torch.cuda.synchronize()
         assert torch.equal(c, c_all[off + r0:off + r0 + cnt])
         assert torch.equal(k, k_all[off + r0:off + r0 + cnt])
+        c, k = P.gbs_cumulants_shard(40, s, 5, r0, cnt, conv)
+        torch.cuda.synchronize()
+        # two FP64 evaluations: each within the oracle tolerance of the exact value
+        ranks = np.arange(r0, r0 + cnt, dtype=np.int64)
+        vmu, vkap = O.c_error_floor(inst.sigma, 5, ranks, conv)
+        cd = c_def[off + r0:off + r0 + cnt].cpu().numpy()
+        kd = k_def[off + r0:off + r0 + cnt].cpu().numpy()
+        assert_within(c.cpu().numpy(), cd, 2 * fp64_tolerance(cd, vmu), f"corr [{r0}, +{cnt})")
+        assert_within(k.cpu().numpy(), kd, 2 * fp64_tolerance(kd, vkap), f"cum [{r0}, +{cnt})")
     ranks = np.arange(123_457, 123_457 + 2000, dtype=np.int64)
     c, k = P.gbs_cumulants_shard(40, s, 5, 123_457, 2000, conv)
     rc, rk = O.c_forward_sample(inst.sigma, 5, ranks, conv)
     vmu, vkap = O.c_error_floor(inst.sigma, 5, ranks, conv)
     assert_within(c.cpu().numpy(), rc, fp64_tolerance(rc, vmu), "M=40 corr")
     assert_within(k.cpu().numpy(), rk, fp64_tolerance(rk, vkap), "M=40 cum")
+
+
+@pytest.mark.parametrize("order", [3, 4, 5])
+def test_shard_every_rank_small(P, order):
+    """M = 13: every subset of orders 3-5 against the oracle, as one range, as
+    many ragged ranges (the same bits), and without the correlator output."""
+    import torch
+    _say("case: shard M=13", order)
+    inst = G.make_instance("m144_k5", M=13, seed=13)
+    s = _dev(inst.sigma)
+    n = math.comb(13, order)
+    ranks = np.arange(n, dtype=np.int64)
+    rc, rk = O.c_forward_sample(inst.sigma, order, ranks)
+    vmu, vkap = O.c_error_floor(inst.sigma, order, ranks)
+    c, k = P.gbs_cumulants_shard(13, s, order, 0, n, 0)
+    assert_within(c.cpu().numpy(), rc, fp64_tolerance(rc, vmu), f"d={order} corr")
+    assert_within(k.cpu().numpy(), rk, fp64_tolerance(rk, vkap), f"d={order} cum")
+    cuts = [0, 1, 2, 7, 30, n // 2, n // 2 + 1, n - 3, n]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        if b <= a:
+            continue
+        c2, k2 = P.gbs_cumulants_shard(13, s, order, a, b - a, 0)
+        torch.cuda.synchronize()
+        assert torch.equal(c2, c[a:b]) and torch.equal(k2, k[a:b]), (a, b)
+    _, k3 = P.gbs_cumulants_shard(13, s, order, 0, n, 0, want_corr=False)
+    assert torch.equal(k3, k)
 
 
 @pytest.fixture(scope="module")
