@@ -149,8 +149,11 @@ __device__ __forceinline__ void a_tree(const double* rec, const double (&C)[2 * 
   }
 }
 
+// Four waves per SIMD: the per-subset recursion would take 160 VGPRs (three
+// waves); capped at 128 it spills four, and the extra wave hides more of the
+// Q and LDS latency.
 template <int D, int CONV, bool WC, bool WK>
-__global__ __launch_bounds__(kShardThreads) void forward_shard_kernel(
+__global__ __launch_bounds__(kShardThreads) __attribute__((amdgpu_waves_per_eu(4))) void forward_shard_kernel(
     const double* __restrict__ Qi, int M, uint64_t rank0, uint64_t count, uint64_t beta0,
     uint64_t nbeta, uint64_t ntiles, const uint64_t* __restrict__ binom,
     double* __restrict__ corr, double* __restrict__ cum, DeviceStatus* __restrict__ st) {
