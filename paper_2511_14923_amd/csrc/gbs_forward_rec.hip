@@ -214,13 +214,11 @@ __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restri
     else colex_unrank_est<D>(r, M, gbin, ld, s);
     const int a = s[0], e = s[D - 1];
     constexpr bool PDROP = D >= 3 && !MIXED;
-    // binomials C(s_i, k) for the rank arithmetic
-    Idx cb[D][D + 1];
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-      for (int kk = 1; kk <= D; ++kk)
-        cb[i][kk] = LDS_BIN ? (Idx)bin[kk * ld + s[i]] : (Idx)gbin[kk * ld + s[i]];
+    // binomials C(s_i, k) for the rank arithmetic, read where they are used (a
+    // per-thread array of them would live in scratch memory)
+    auto cb = [&](int i, int kk) -> Idx {
+      return LDS_BIN ? (Idx)bin[kk * ld + s[i]] : (Idx)gbin[kk * ld + s[i]];
+    };
     constexpr int UDROP_D = (D >= 3) ? (FULL ^ (1 << (D - 3))) : -1;           // B minus d
     constexpr int UDROP_DE = (D >= 3) ? (FULL ^ (1 << (D - 3)) ^ (1 << (D - 2))) : -1;  // B minus d, e
     double pu[NU];
@@ -234,7 +232,7 @@ __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restri
         int j = 0;
 #pragma unroll
         for (int i = 0; i < NB; ++i)
-          if (u & (1 << i)) rk += cb[i + 1][(j++) + 2];
+          if (u & (1 << i)) rk += cb(i + 1, (j++) + 2);
         pu[u] = load_at(tab.p[popcount_c((unsigned)u) + 1], rk);
       }
       mw[0] = 1.0;
@@ -244,7 +242,7 @@ __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restri
         int j = 0;
 #pragma unroll
         for (int i = 0; i < NB; ++i)
-          if (w & (1 << i)) rk += cb[i + 1][(j++) + 1];
+          if (w & (1 << i)) rk += cb(i + 1, (j++) + 1);
         mw[w] = load_at(tab.m[popcount_c((unsigned)w)], rk);
       }
     };
@@ -352,8 +350,8 @@ __global__ __launch_bounds__(256) void forward_rec_kernel(const double* __restri
           int j = 0;
 #pragma unroll
           for (int i = 0; i < D - 1; ++i)
-            if (Y & (1 << i)) rk += cb[i][(j++) + 1];
-          rk += cb[D - 1][j + 1];
+            if (Y & (1 << i)) rk += cb(i, (j++) + 1);
+          rk += cb(D - 1, j + 1);
           Kv[Y] = load_at(tab.k[j + 1], rk);
         }
       }
