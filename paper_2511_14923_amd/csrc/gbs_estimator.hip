@@ -201,9 +201,52 @@ __global__ __launch_bounds__(kEstThreads) void count_kernel(const uint64_t* __re
 struct KstatCoef {
   int n;                       // partitions of [d]
   float pad;
-  double coef[52];             // c_N(tau) for the moment form (prod of s_B / N)
-  uint32_t blocks[52][5];      // block masks of tau (0 = none)
+  double coef[52];             // c_N(tau) for the moment form (prod of s_B / N), partitions
+                               // in make_parts order
 };
+
+// The partitions of [D] in the order kstat_coefficients lists them (restricted
+// growth strings in lexicographic order), each as its block masks in ascending
+// order (0 = no block), built at compile time so that the kernel's loop over
+// them unrolls with constant indices into the register array of moments.
+template <int D>
+struct PartTable {
+  int n = 0;
+  uint32_t blk[52][5] = {};
+};
+
+template <int D>
+constexpr PartTable<D> make_parts() {
+  PartTable<D> T;
+  int lab[D] = {};
+  for (;;) {
+    uint32_t mk[D] = {};
+    int nb = 0;
+    for (int i = 0; i < D; ++i) {
+      mk[lab[i]] |= 1u << i;
+      nb = lab[i] + 1 > nb ? lab[i] + 1 : nb;
+    }
+    for (int i = 1; i < nb; ++i)  // ascending masks (insertion sort)
+      for (int j = i; j > 0 && mk[j - 1] > mk[j]; --j) {
+        const uint32_t t = mk[j];
+        mk[j] = mk[j - 1];
+        mk[j - 1] = t;
+      }
+    for (int b = 0; b < nb; ++b) T.blk[T.n][b] = mk[b];
+    ++T.n;
+    // next restricted growth string: the last position that can grow
+    int i = D - 1;
+    for (; i >= 1; --i) {
+      int mx = 0;
+      for (int j = 0; j < i; ++j) mx = lab[j] > mx ? lab[j] : mx;
+      if (lab[i] <= mx) break;
+    }
+    if (i < 1) break;
+    ++lab[i];
+    for (int j = i + 1; j < D; ++j) lab[j] = 0;
+  }
+  return T;
+}
 
 template <int D>
 __global__ void kstat_kernel(const uint32_t* const* __restrict__ cnt, int M, uint64_t count,
@@ -224,12 +267,14 @@ __global__ void kstat_kernel(const uint32_t* const* __restrict__ cnt, int M, uin
         if (B & (1 << i)) rk += binom[(++j) * kBinLd + s[i]];
       m[B] = (double)cnt[popcount_c((unsigned)B)][rk] * invN;
     }
+    constexpr PartTable<D> kParts = make_parts<D>();
     double k = 0.0, comp = 0.0;
-    for (int t = 0; t < cf->n; ++t) {
+#pragma unroll
+    for (int t = 0; t < kParts.n; ++t) {
       double v = cf->coef[t];
 #pragma unroll
       for (int b = 0; b < D; ++b) {
-        const uint32_t blk = cf->blocks[t][b];
+        const uint32_t blk = kParts.blk[t][b];
         if (blk) v *= m[blk];
       }
       const double y = k + v;  // compensated sum
@@ -361,7 +406,6 @@ void kstat_coefficients(int d, double N, KstatCoef* out) {
     double Np = 1.0;
     for (size_t b = 0; b < pm[t].size(); ++b) Np *= N;
     out->coef[t] = coef[t] * Np;
-    for (int b = 0; b < 5; ++b) out->blocks[t][b] = b < (int)pm[t].size() ? pm[t][b] : 0u;
   }
 }
 
