@@ -172,14 +172,15 @@ def test_batched_timing_entries(P):
         assert _agree(corr, c1) and _agree(cum, k1)
 
 
-def test_order5_tables_scratch_and_fallback(P, c_oracle):
+@pytest.mark.parametrize("conv", [0, 1], ids=["click", "parity"])
+def test_order5_tables_scratch_and_fallback(P, c_oracle, conv):
     """K = 5 over instances of uneven M, some without correlator outputs (the
     group kernel then keeps the lower-order correlators in plan scratch), and
     one of M = 150, whose order 5 (more than 2^29 subsets) falls back to the
     all-minors launch while orders 3 and 4 run on the group kernel; sampled
     outputs of every order against the C oracle."""
     import torch
-    _say("case: batch K=5 scratch + fallback")
+    _say("case: batch K=5 scratch + fallback", conv)
     Ms = [150, 23, 9, 31, 5]
     batch = [G.make_instance("m144_k5", M=m, seed=300 + m) for m in Ms]
     bufs = []
@@ -188,14 +189,14 @@ def test_order5_tables_scratch_and_fallback(P, c_oracle):
         n = O.total_outputs(inst.M, 5)
         corr = torch.empty(n, dtype=torch.float64, device="cuda:0") if j % 2 == 0 else None
         bufs.append((inst.M, s, corr, torch.empty(n, dtype=torch.float64, device="cuda:0")))
-    P.gbs_cumulants_batched(bufs, 5, 0)
+    P.gbs_cumulants_batched(bufs, 5, conv)
     torch.cuda.synchronize()
     for i, (inst, (M, _, corr, cum)) in enumerate(zip(batch, bufs)):
         for d in range(1, 6):
             n = math.comb(M, d)
             ranks = G.random_ranks(n, 300 if M > 100 else 2000, seed=700 * i + d)
-            rc, rk = O.c_forward_sample(inst.sigma, d, ranks)
-            vmu, vkap = O.c_error_floor(inst.sigma, d, ranks)
+            rc, rk = O.c_forward_sample(inst.sigma, d, ranks, conv)
+            vmu, vkap = O.c_error_floor(inst.sigma, d, ranks, conv)
             idx = torch.from_numpy(O.order_offset(M, d) + ranks.astype(np.int64)).to("cuda:0")
             if corr is not None:
                 got = corr[idx].cpu().numpy()
@@ -204,7 +205,7 @@ def test_order5_tables_scratch_and_fallback(P, c_oracle):
             assert_within(got, rk, fp64_tolerance(rk, vkap), f"M={M} cum d={d}")
     # the small instances also agree with single calls everywhere
     for (M, s, corr, cum) in bufs[1:]:
-        c1, k1 = P.gbs_cumulants(M, s, 5, 0)
+        c1, k1 = P.gbs_cumulants(M, s, 5, conv)
         assert _agree(cum, k1), M
         if corr is not None:
             assert _agree(corr, c1), M

@@ -68,29 +68,30 @@ def test_shard_is_a_slice_of_the_full_pass(P, conv):
     assert_within(k.cpu().numpy(), rk, fp64_tolerance(rk, vkap), "M=40 cum")
 
 
+@pytest.mark.parametrize("conv", [0, 1], ids=["click", "parity"])
 @pytest.mark.parametrize("order", [3, 4, 5])
-def test_shard_every_rank_small(P, order):
+def test_shard_every_rank_small(P, order, conv):
     """M = 13: every subset of orders 3-5 against the oracle, as one range, as
     many ragged ranges (the same bits), and without the correlator output."""
     import torch
-    _say("case: shard M=13", order)
+    _say("case: shard M=13", order, conv)
     inst = G.make_instance("m144_k5", M=13, seed=13)
     s = _dev(inst.sigma)
     n = math.comb(13, order)
     ranks = np.arange(n, dtype=np.int64)
-    rc, rk = O.c_forward_sample(inst.sigma, order, ranks)
-    vmu, vkap = O.c_error_floor(inst.sigma, order, ranks)
-    c, k = P.gbs_cumulants_shard(13, s, order, 0, n, 0)
+    rc, rk = O.c_forward_sample(inst.sigma, order, ranks, conv)
+    vmu, vkap = O.c_error_floor(inst.sigma, order, ranks, conv)
+    c, k = P.gbs_cumulants_shard(13, s, order, 0, n, conv)
     assert_within(c.cpu().numpy(), rc, fp64_tolerance(rc, vmu), f"d={order} corr")
     assert_within(k.cpu().numpy(), rk, fp64_tolerance(rk, vkap), f"d={order} cum")
     cuts = [0, 1, 2, 7, 30, n // 2, n // 2 + 1, n - 3, n]
     for a, b in zip(cuts[:-1], cuts[1:]):
         if b <= a:
             continue
-        c2, k2 = P.gbs_cumulants_shard(13, s, order, a, b - a, 0)
+        c2, k2 = P.gbs_cumulants_shard(13, s, order, a, b - a, conv)
         torch.cuda.synchronize()
         assert torch.equal(c2, c[a:b]) and torch.equal(k2, k[a:b]), (a, b)
-    _, k3 = P.gbs_cumulants_shard(13, s, order, 0, n, 0, want_corr=False)
+    _, k3 = P.gbs_cumulants_shard(13, s, order, 0, n, conv, want_corr=False)
     assert torch.equal(k3, k)
 
 
