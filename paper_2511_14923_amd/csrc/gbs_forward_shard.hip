@@ -153,7 +153,8 @@ __device__ __forceinline__ void a_tree(const double* rec, const double (&C)[2 * 
 // waves); capped at 128 it spills four, and the extra wave hides more of the
 // Q and LDS latency.
 template <int D, int CONV, bool WC, bool WK>
-__global__ __launch_bounds__(kShardThreads) __attribute__((amdgpu_waves_per_eu(4))) void forward_shard_kernel(
+__global__ __launch_bounds__(kShardThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void forward_shard_kernel(
     const double* __restrict__ Qi, int M, uint64_t rank0, uint64_t count, uint64_t beta0,
     uint64_t nbeta, uint64_t ntiles, const uint64_t* __restrict__ binom,
     double* __restrict__ corr, double* __restrict__ cum, DeviceStatus* __restrict__ st) {
@@ -354,18 +355,16 @@ hipError_t launch_forward_shard(int d, int M, int flags, const double* Qi, const
   if (d < 3 || d > kMaxOrder) return hipErrorInvalidValue;
   const uint64_t beta0 = top_rank(d, rank0);
   const uint64_t nbeta = top_rank(d, rank0 + count - 1) - beta0 + 1;
+  using Launch = hipError_t (*)(int, const double*, const uint64_t*, uint64_t, uint64_t,
+                                 uint64_t, uint64_t, double*, double*, DeviceStatus*, hipStream_t);
   const bool par = (flags & GBS_PARITY) != 0;
+  Launch fn;
   switch (d) {
-    case 3:
-      return par ? launch_shard_t<3, GBS_PARITY>(M, Qi, binom, rank0, count, beta0, nbeta, corr, cum, st, s)
-                 : launch_shard_t<3, GBS_CLICK>(M, Qi, binom, rank0, count, beta0, nbeta, corr, cum, st, s);
-    case 4:
-      return par ? launch_shard_t<4, GBS_PARITY>(M, Qi, binom, rank0, count, beta0, nbeta, corr, cum, st, s)
-                 : launch_shard_t<4, GBS_CLICK>(M, Qi, binom, rank0, count, beta0, nbeta, corr, cum, st, s);
-    default:
-      return par ? launch_shard_t<5, GBS_PARITY>(M, Qi, binom, rank0, count, beta0, nbeta, corr, cum, st, s)
-                 : launch_shard_t<5, GBS_CLICK>(M, Qi, binom, rank0, count, beta0, nbeta, corr, cum, st, s);
+    case 3: fn = par ? launch_shard_t<3, GBS_PARITY> : launch_shard_t<3, GBS_CLICK>; break;
+    case 4: fn = par ? launch_shard_t<4, GBS_PARITY> : launch_shard_t<4, GBS_CLICK>; break;
+    default: fn = par ? launch_shard_t<5, GBS_PARITY> : launch_shard_t<5, GBS_CLICK>; break;
   }
+  return fn(M, Qi, binom, rank0, count, beta0, nbeta, corr, cum, st, s);
 }
 
 }  // namespace gbs
