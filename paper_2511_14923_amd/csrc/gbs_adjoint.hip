@@ -144,6 +144,28 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Workgroups of up to this many threads share one superset sum (the sigma-bar
+// kernel, whose per-superset inverse needs about 200 registers, up to
+// kSigmaThreads).
+constexpr int kSumThreads = 1024;
+constexpr int kSigmaThreads = 256;
+
+// Sum over the workgroup in a fixed order (lanes by the butterfly, then the
+// waves in index order): deterministic for a given launch shape.  Valid in
+// thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double part[kSumThreads / kWave];
+  __syncthreads();  // thread 0 has read the previous call's partial sums
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) part[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += part[i];
+  return t;
+}
+
 struct Offsets {
   int64_t off[kMaxOrder + 2];  // start of order-d block, off[1] = 0
 };
@@ -180,22 +202,22 @@ __global__ void d1_kernel(const double* __restrict__ m, int M, int K, Offsets o,
   }
 }
 
-// mbar(B) for every B of order k (one wavefront per B).
-__global__ __launch_bounds__(kWave) void mbar_kernel(int M, int K, int k, Offsets o,
+// mbar(B) for every B of order k (one workgroup per B, its threads striding
+// over the supersets).
+__global__ __launch_bounds__(kSumThreads) void mbar_kernel(int M, int K, int k, Offsets o,
                                                      const uint64_t* __restrict__ bin,
                                                      const double* __restrict__ gm,
                                                      const double* __restrict__ gk,
                                                      const double* __restrict__ d1,
                                                      double* __restrict__ mbar) {
   const uint64_t rb = blockIdx.x;
-  const int lane = threadIdx.x;
   int B[kMaxOrder];
   unrank_dyn(bin, rb, k, M, B);
   double acc = 0.0;
   if (gk && k < K) {
     const int u = M - k;
     const uint64_t nx = count_sized(bin, 1, K - k, u);
-    for (uint64_t i = lane; i < nx; i += kWave) {
+    for (uint64_t i = threadIdx.x; i < nx; i += blockDim.x) {
       int j;
       uint64_t rx;
       flat_to_sized(bin, i, 1, K - k, u, &j, &rx);
@@ -206,8 +228,8 @@ __global__ __launch_bounds__(kWave) void mbar_kernel(int M, int K, int k, Offset
       acc = fma(gk[o.off[n] + rank_sorted(bin, U, n)], d1[o.off[j] + rank_sorted(bin, X, j)], acc);
     }
   }
-  acc = wave_sum(acc);
-  if (lane == 0) {
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) {
     const int64_t at = o.off[k] + (int64_t)rb;
     double v = acc;
     if (gk) v += gk[at];
@@ -216,19 +238,36 @@ __global__ __launch_bounds__(kWave) void mbar_kernel(int M, int K, int k, Offset
   }
 }
 
-// pbar(T) for every T of order t (one wavefront per T).
-__global__ __launch_bounds__(kWave) void pbar_kernel(int M, int K, int t, int parity, Offsets o,
+// The top order K has no proper supersets: mbar = gk + gm and
+// pbar = (-1)^K mbar (click) or (-2)^K (-1)^K mbar (parity), one thread per subset.
+__global__ void top_order_kernel(int64_t off, uint64_t count, int K, int parity,
+                                 const double* __restrict__ gm, const double* __restrict__ gk,
+                                 double* __restrict__ mbar, double* __restrict__ pbar) {
+  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= count) return;
+  const int64_t at = off + (int64_t)r;
+  double v = 0.0;
+  if (gk) v += gk[at];
+  if (gm) v += gm[at];
+  mbar[at] = v;
+  double coef = (K & 1) ? -1.0 : 1.0;
+  if (parity) coef *= (K & 1) ? -(double)(1 << K) : (double)(1 << K);
+  pbar[at] = coef * v;
+}
+
+// pbar(T) for every T of order t (one workgroup per T, its threads striding
+// over the supersets).
+__global__ __launch_bounds__(kSumThreads) void pbar_kernel(int M, int K, int t, int parity, Offsets o,
                                                      const uint64_t* __restrict__ bin,
                                                      const double* __restrict__ mbar,
                                                      double* __restrict__ pbar) {
   const uint64_t rt = blockIdx.x;
-  const int lane = threadIdx.x;
   int T[kMaxOrder];
   unrank_dyn(bin, rt, t, M, T);
   const int u = M - t;
   const uint64_t nx = count_sized(bin, 0, K - t, u);
   double acc = 0.0;
-  for (uint64_t i = lane; i < nx; i += kWave) {
+  for (uint64_t i = threadIdx.x; i < nx; i += blockDim.x) {
     int j;
     uint64_t rx;
     flat_to_sized(bin, i, 0, K - t, u, &j, &rx);
@@ -239,8 +278,8 @@ __global__ __launch_bounds__(kWave) void pbar_kernel(int M, int K, int t, int pa
     const double v = mbar[o.off[n] + rank_sorted(bin, U, n)];
     acc += (parity && (n & 1)) ? -v : v;
   }
-  acc = wave_sum(acc);
-  if (lane == 0) {
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) {
     // click: (-1)^t;  parity: (-2)^t (the (-1)^|B| factor is inside the sum)
     double coef = (t & 1) ? -1.0 : 1.0;
     if (parity) coef *= (double)(1 << t);
@@ -349,28 +388,33 @@ __device__ __forceinline__ void base_inverse_dispatch(const double* __restrict__
 }
 
 // One wavefront per mode pair (i <= j): the 2x2 block of dL/dsigma.
-__global__ __launch_bounds__(kWave) void sigma_bar_kernel(const double* __restrict__ Qi, int M, int K,
-                                                          Offsets o,
-                                                          const uint64_t* __restrict__ bin,
-                                                          const double* __restrict__ ptab,
-                                                          const double* __restrict__ pbar,
-                                                          double* __restrict__ gsig,
-                                                          DeviceStatus* __restrict__ st) {
-  // pair index -> (i, j), i <= j, colex over pairs with repetition:
-  // blockIdx = j (j+1)/2 + i
+// One workgroup per mode pair (i, j): the diagonal pairs (many more supersets,
+// wide workgroups) and the pairs i < j (colex, blockIdx = j (j - 1) / 2 + i)
+// are separate launches.
+__global__ __launch_bounds__(kSigmaThreads) void sigma_bar_kernel(const double* __restrict__ Qi,
+                                                                int M, int K, int diag, Offsets o,
+                                                                const uint64_t* __restrict__ bin,
+                                                                const double* __restrict__ ptab,
+                                                                const double* __restrict__ pbar,
+                                                                double* __restrict__ gsig,
+                                                                DeviceStatus* __restrict__ st) {
   const int64_t pid = blockIdx.x;
-  int j = (int)((sqrt(8.0 * (double)pid + 1.0) - 1.0) / 2.0);
-  while ((int64_t)j * (j + 1) / 2 > pid) --j;
-  while ((int64_t)(j + 1) * (j + 2) / 2 <= pid) ++j;
-  const int i = (int)(pid - (int64_t)j * (j + 1) / 2);
-  const int lane = threadIdx.x;
+  int i, j;
+  if (diag) {
+    i = j = (int)pid;
+  } else {
+    j = (int)((1.0 + sqrt(8.0 * (double)pid + 1.0)) / 2.0);
+    while ((int64_t)j * (j - 1) / 2 > pid) --j;
+    while ((int64_t)(j + 1) * j / 2 <= pid) ++j;
+    i = (int)(pid - (int64_t)j * (j - 1) / 2);
+  }
   int base[2] = {i, j};
   const int nb = (i == j) ? 1 : 2;
   const int u = M - nb;
   const uint64_t nx = count_sized(bin, 0, K - nb, u);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   bool bad = false;
-  for (uint64_t q = lane; q < nx; q += kWave) {
+  for (uint64_t q = threadIdx.x; q < nx; q += blockDim.x) {
     int jx;
     uint64_t rx;
     flat_to_sized(bin, q, 0, K - nb, u, &jx, &rx);
@@ -390,9 +434,9 @@ __global__ __launch_bounds__(kWave) void sigma_bar_kernel(const double* __restri
     for (int e = 0; e < 4; ++e) acc[e] = fma(w, G[e], acc[e]);
   }
 #pragma unroll
-  for (int e = 0; e < 4; ++e) acc[e] = wave_sum(acc[e]);
-  if (bad) latch_failure(st, 0, pid);
-  if (lane == 0) {
+  for (int e = 0; e < 4; ++e) acc[e] = block_sum(acc[e]);
+  if (bad) latch_failure(st, 0, (int64_t)j * (j + 1) / 2 + i);  // pair index, i <= j
+  if (threadIdx.x == 0) {
     const size_t n2 = 2 * (size_t)M;
     // interleaved (2i + a, 2j + b) -> xxpp (i + a M, j + b M)
     const size_t xi = i, pi = i + M, xj = j, pj = j + M;
@@ -428,28 +472,62 @@ hipError_t launch_adjoint(int M, int K, int flags, const double* Qi, const uint6
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = timing_end(s);
   }
-  for (int k = 1; k <= K && e == hipSuccess; ++k) {
+  // threads per workgroup for a sum over n supersets: whole wavefronts, at most kSumThreads
+  auto threads_for = [](uint64_t n, int cap = kSumThreads) {
+    const uint64_t w = std::max<uint64_t>(1, std::min<uint64_t>((n + kWave - 1) / kWave,
+                                                                (uint64_t)(cap / kWave)));
+    return (unsigned)(w * kWave);
+  };
+  auto supersets = [&](int k, int jmin) {  // sum_{j = jmin}^{K-k} C(M - k, j)
+    uint64_t n = 0;
+    for (int j = jmin; j <= K - k; ++j) n += host_binom(M - k, j);
+    return n;
+  };
+  for (int k = 1; k < K && e == hipSuccess; ++k) {
     e = timing_begin(s, GBS_STAGE_ADJOINT, k);
     if (e == hipSuccess)
-      hipLaunchKernelGGL(mbar_kernel, dim3((unsigned)host_binom(M, k)), dim3(kWave), 0, s, M, K, k,
-                         o, binom, gm, gk, d1, mbar);
+      hipLaunchKernelGGL(mbar_kernel, dim3((unsigned)host_binom(M, k)),
+                         dim3(gk ? threads_for(supersets(k, 1)) : kWave), 0, s, M, K, k, o, binom,
+                         gm, gk, d1, mbar);
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = timing_end(s);
   }
-  for (int t = 1; t <= K && e == hipSuccess; ++t) {
+  if (e == hipSuccess) {  // order K: mbar and pbar together
+    e = timing_begin(s, GBS_STAGE_ADJOINT, K);
+    const uint64_t cnt = host_binom(M, K);
+    if (e == hipSuccess)
+      hipLaunchKernelGGL(top_order_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                         o.off[K], cnt, K, parity, gm, gk, mbar, pbar);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = timing_end(s);
+  }
+  for (int t = 1; t < K && e == hipSuccess; ++t) {
     e = timing_begin(s, GBS_STAGE_ADJOINT, t);
     if (e == hipSuccess)
-      hipLaunchKernelGGL(pbar_kernel, dim3((unsigned)host_binom(M, t)), dim3(kWave), 0, s, M, K, t,
-                         parity, o, binom, mbar, pbar);
+      hipLaunchKernelGGL(pbar_kernel, dim3((unsigned)host_binom(M, t)),
+                         dim3(threads_for(supersets(t, 0))), 0, s, M, K, t, parity, o, binom, mbar,
+                         pbar);
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = timing_end(s);
   }
   if (e == hipSuccess) {
     e = timing_begin(s, GBS_STAGE_ADJOINT, 0);
-    const unsigned pairs = (unsigned)((int64_t)M * (M + 1) / 2);
+    // supersets of {i} (diagonal) and of {i, j}: sum_j C(M - nb, j), j <= K - nb
+    auto sets = [&](int nb) {
+      uint64_t n = 0;
+      for (int q = 0; q <= K - nb; ++q) n += host_binom(M - nb, q);
+      return n;
+    };
     if (e == hipSuccess)
-      hipLaunchKernelGGL(sigma_bar_kernel, dim3(pairs), dim3(kWave), 0, s, Qi, M, K, o, binom, ptab,
-                         pbar, gsig, st);
+      hipLaunchKernelGGL(sigma_bar_kernel, dim3((unsigned)M),
+                         dim3(threads_for(sets(1), kSigmaThreads)), 0, s, Qi, M, K, 1, o, binom,
+                         ptab, pbar, gsig, st);
+    if (e == hipSuccess) e = hipGetLastError();
+    const unsigned pairs = (unsigned)((int64_t)M * (M - 1) / 2);
+    if (e == hipSuccess && pairs > 0)
+      hipLaunchKernelGGL(sigma_bar_kernel, dim3(pairs),
+                         dim3(threads_for(sets(2), kSigmaThreads)), 0, s, Qi, M, K, 0, o, binom,
+                         ptab, pbar, gsig, st);
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = timing_end(s);
   }
