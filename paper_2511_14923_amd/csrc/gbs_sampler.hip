@@ -276,10 +276,10 @@ __global__ __launch_bounds__(64 * kSampWaves) void sampler_kernel(
         // Loops are split where the order of the elided bits changes, so
         // that each runs over consecutive table entries without a branch.
         double v3 = 0.0;
-#pragma unroll 2
+#pragma unroll 4
         for (int i = 1; i < e; ++i)
           v3 += flip(kap[o2 + r1(i)] * t.p2(n - 1, e, i), x.get(i) ^ xn);
-#pragma unroll 2
+#pragma unroll 4
         for (int i = e + 1; i < n; ++i)
           v3 += flip(kap[o2 + r1(i)] * t.p2(n - 1, i, e), x.get(i) ^ xn);
         double v = fma(0.25, v3, h * t.p1(n - 1, e));
@@ -291,12 +291,12 @@ __global__ __launch_bounds__(64 * kSampWaves) void sampler_kernel(
           const uint32_t ki = o3 + r2(i);
           double ai = 0.0;
           if (i < e) {
-#pragma unroll 2
+#pragma unroll 4
             for (int j = 1; j < i; ++j) ai += flip(kap[ki + r1(j)] * t.p2(e - 1, i, j), x.get(j));
           } else {
-#pragma unroll 2
+#pragma unroll 4
             for (int j = 1; j < e; ++j) ai += flip(kap[ki + r1(j)] * t.p2(i - 1, e, j), x.get(j));
-#pragma unroll 2
+#pragma unroll 4
             for (int j = e + 1; j < i; ++j) ai += flip(kap[ki + r1(j)] * t.p2(i - 1, j, e), x.get(j));
           }
           v += flip(0.125 * A * ai, x.get(i) ^ xn);
@@ -309,13 +309,13 @@ __global__ __launch_bounds__(64 * kSampWaves) void sampler_kernel(
           // (a, b, c): i, e, d in decreasing order.  Terms i < e have a = e and
           // share the factor p+(n-1..e+1); terms i > e have (a, b, c) = (i, e, d).
           double below = 0.0, above = 0.0;
-#pragma unroll 2
+#pragma unroll 4
           for (int i = 1; i < d; ++i)
             below += flip(kap[o2 + r1(i)] * t.p2(e - 1, d, i), x.get(i) ^ xn);
-#pragma unroll 2
+#pragma unroll 4
           for (int i = d + 1; i < e; ++i)
             below += flip(kap[o2 + r1(i)] * t.p2(e - 1, i, d), x.get(i) ^ xn);
-#pragma unroll 2
+#pragma unroll 4
           for (int i = e + 1; i < n; ++i)
             above += flip(kap[o2 + r1(i)] * t.pp(n - 1, i + 1) * t.p2(i - 1, e, d), x.get(i) ^ xn);
           const double v = h * t.p2(n - 1, e, d) + 0.25 * fma(t.pp(n - 1, e + 1), below, above);
