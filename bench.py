@@ -135,6 +135,13 @@ def precision_errors(torch, P, corr64, cum64, corrmx, cummx):
     return out
 
 
+def fp64_tolerance(np, ref, scale):
+    """The FP64 parity tolerance of the click convention: 1e-10 max(|ref|,
+    1e-4 scale), scale the summand magnitude of the sum that gives the output
+    (oracle.c_tolerance_scale)."""
+    return 1e-10 * np.maximum(np.abs(ref), 1e-4 * scale)
+
+
 def fp64_parity_sample(np, O, G, inst, corr, cum, n=3000, mu=None):
     """Sampled FP64 outputs against the oracle (displaced when mu is given):
     worst |delta| / tolerance."""
@@ -143,13 +150,12 @@ def fp64_parity_sample(np, O, G, inst, corr, cum, n=3000, mu=None):
         cnt = math.comb(M, d)
         ranks = G.random_ranks(cnt, min(n, cnt), seed=900 + d)
         rc, rk = O.c_forward_sample(inst.sigma, d, ranks, mu=mu)
-        vmu, vkap = O.c_error_floor(inst.sigma, d, ranks, mu=mu)
+        smu, skap = O.c_tolerance_scale(inst.sigma, d, ranks, mu=mu)
         off = O.order_offset(M, d)
         gc = corr[off + ranks]
         gk = cum[off + ranks]
-        for got, ref, v in ((gc, rc, vmu), (gk, rk, vkap)):
-            tol = 1e-10 * np.abs(ref) + O.FLOOR_FACTOR * O.U64 * v
-            worst = max(worst, float(np.max(np.abs(got - ref) / tol)))
+        for got, ref, v in ((gc, rc, smu), (gk, rk, skap)):
+            worst = max(worst, float(np.max(np.abs(got - ref) / fp64_tolerance(np, ref, v))))
     return worst
 
 

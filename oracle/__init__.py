@@ -549,6 +549,11 @@ def _c():
         lib.oracle_forward_sample_mu.restype = i32
         lib.oracle_error_floor_mu.argtypes = [i32, dp, dp, i32, lp, i64, i32, dp, dp, i32]
         lib.oracle_error_floor_mu.restype = i32
+        lib.oracle_forward_range_mu.argtypes = [i32, dp, dp, i32, i64, i64, i32, dp, dp, dp, dp,
+                                                i32]
+        lib.oracle_forward_range_mu.restype = i32
+        lib.oracle_tolerance_scale_mu.argtypes = [i32, dp, dp, i32, lp, i64, i32, dp, dp, i32]
+        lib.oracle_tolerance_scale_mu.restype = i32
         lib.oracle_threads.argtypes = [i32]
         lib.oracle_threads.restype = i32
         _lib = lib
@@ -642,3 +647,49 @@ def c_error_floor(sigma: np.ndarray, d: int, ranks, convention: int = CLICK,
     if rc != 0:
         raise RuntimeError(f"oracle_error_floor failed ({rc})")
     return vmu, vkap
+
+
+def c_forward_range(sigma: np.ndarray, d: int, rank0: int, count: int,
+                    convention: int = CLICK, threads: int = 0, mu=None, scales: bool = False):
+    """(corr, cum) of the order-d subsets with colex ranks rank0 .. rank0+count-1;
+    with ``scales`` also (smu, skap) of ``c_tolerance_scale`` for the same subsets."""
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    M = sigma.shape[0] // 2
+    corr = np.empty(count)
+    cum = np.empty(count)
+    smu = np.empty(count) if scales else None
+    skap = np.empty(count) if scales else None
+    null = ctypes.POINTER(ctypes.c_double)()
+    keep, mptr = _mu_arg(mu, M)
+    rc = _c().oracle_forward_range_mu(M, _dptr(sigma), mptr, d, int(rank0), int(count),
+                                      convention, _dptr(corr), _dptr(cum),
+                                      _dptr(smu) if scales else null,
+                                      _dptr(skap) if scales else null, threads)
+    if rc != 0:
+        raise RuntimeError(f"oracle_forward_range failed ({rc})")
+    return (corr, cum, smu, skap) if scales else (corr, cum)
+
+
+def c_tolerance_scale(sigma: np.ndarray, d: int, ranks, convention: int = CLICK,
+                      threads: int = 0, mu=None) -> tuple:
+    """(smu, skap): the summand magnitudes of the two sums of each sampled output.
+
+    smu(S) = sum_{T subset S} |w_T| p(T) for the correlator (inclusion-exclusion,
+    w_T = (-1)^|T| click or (-2)^|T| parity); skap(S) = sum over set partitions of
+    |w(pi)| prod_{B in pi} |m(B)| for the cumulant (the partition sum of Eq.
+    cumulant_corr_main).  An FP64 evaluation of either sum is accurate to a
+    small multiple of u times that scale, however much the terms cancel, so the
+    stated tolerance is |delta| <= 1e-10 max(|ref|, 1e-4 scale).
+    """
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    M = sigma.shape[0] // 2
+    ranks = np.ascontiguousarray(ranks, dtype=np.int64)
+    smu = np.empty(len(ranks))
+    skap = np.empty(len(ranks))
+    keep, mptr = _mu_arg(mu, M)
+    rc = _c().oracle_tolerance_scale_mu(M, _dptr(sigma), mptr, d,
+                                        ranks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        len(ranks), convention, _dptr(smu), _dptr(skap), threads)
+    if rc != 0:
+        raise RuntimeError(f"oracle_tolerance_scale failed ({rc})")
+    return smu, skap

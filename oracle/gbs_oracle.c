@@ -144,9 +144,14 @@ static double weight(int nb) {
 
 static int popc(unsigned x) { int c = 0; while (x) { c += x & 1u; x >>= 1; } return c; }
 
-/* correlator and cumulant of one subset S (ascending, size d) */
+/* correlator and cumulant of one subset S (ascending, size d).  When smu and
+ * skap are not NULL they receive the summand magnitudes of the two sums:
+ *   smu  = sum_{T subset S} |w_T| p(T)  (w_T = (-1)^|T| or (-2)^|T|),
+ *   skap = sum_pi |w(pi)| prod_{B in pi} |m(B)|,
+ * the scales against which the rounding of an FP64 evaluation is measured. */
 static int subset_values(const double* Q, const double* mu, int M, const int* S, int d,
-                         int convention, double* corr, double* cum) {
+                         int convention, double* corr, double* cum, double* smu,
+                         double* skap) {
     double p[1 << KMAX];
     double m[1 << KMAX];
     int full = (1 << d) - 1;
@@ -154,6 +159,7 @@ static int subset_values(const double* Q, const double* mu, int M, const int* S,
         int rc = vacuum_prob(Q, mu, M, S, d, T, &p[T]);
         if (rc) return rc;
     }
+    double mag = 0.0;
     for (unsigned B = 1; B <= (unsigned)full; ++B) {
         nsum acc = {0.0, 0.0};
         for (unsigned T = 0; T <= B; ++T) {
@@ -163,6 +169,7 @@ static int subset_values(const double* Q, const double* mu, int M, const int* S,
             if (convention == 0) term = (t % 2 ? -1.0 : 1.0) * p[T];
             else term = ldexp((t % 2 ? -1.0 : 1.0), t) * p[T];
             nadd(&acc, term);
+            if (B == (unsigned)full) mag += fabs(term);
         }
         double v = nval(&acc);
         if (convention != 0 && (popc(B) % 2)) v = -v;
@@ -170,13 +177,17 @@ static int subset_values(const double* Q, const double* mu, int M, const int* S,
     }
     const partitions* P = &g_parts[d];
     nsum acc = {0.0, 0.0};
+    double kmag = 0.0;
     for (int i = 0; i < P->n; ++i) {
         double prod = weight(P->nblocks[i]);
         for (int b = 0; b < P->nblocks[i]; ++b) prod *= m[P->blocks[i][b]];
         nadd(&acc, prod);
+        kmag += fabs(prod);
     }
     *corr = m[full];
     *cum = nval(&acc);
+    if (smu) *smu = mag;
+    if (skap) *skap = kmag;
     return 0;
 }
 
@@ -217,7 +228,7 @@ int oracle_forward_sample_mu(int M, const double* sigma, const double* mu, int d
     for (int64_t i = 0; i < n; ++i) {
         int S[KMAX];
         unrank(d, ranks[i], S);
-        err |= subset_values(Q, mu, M, S, d, convention, &corr[i], &cum[i]);
+        err |= subset_values(Q, mu, M, S, d, convention, &corr[i], &cum[i], NULL, NULL);
     }
     free(Q);
     return err;
@@ -243,7 +254,8 @@ int oracle_forward_mu(int M, const double* sigma, const double* mu, int K, int c
         for (int64_t r = 0; r < cnt; ++r) {
             int S[KMAX];
             unrank(d, r, S);
-            err |= subset_values(Q, mu, M, S, d, convention, &corr[off + r], &cum[off + r]);
+            err |= subset_values(Q, mu, M, S, d, convention, &corr[off + r], &cum[off + r], NULL,
+                                 NULL);
         }
         off += cnt;
     }
@@ -254,6 +266,54 @@ int oracle_forward_mu(int M, const double* sigma, const double* mu, int K, int c
 int oracle_forward(int M, const double* sigma, int K, int convention, double* corr,
                    double* cum, int threads) {
     return oracle_forward_mu(M, sigma, NULL, K, convention, corr, cum, threads);
+}
+
+/* One contiguous colex rank range of one order: the order-d subsets with ranks
+ * rank0 .. rank0 + count - 1, in rank order, so that a full workload can be
+ * streamed through bounded host buffers.  smu and skap (either may be NULL)
+ * receive the summand magnitudes described at subset_values. */
+int oracle_forward_range_mu(int M, const double* sigma, const double* mu, int d, int64_t rank0,
+                            int64_t count, int convention, double* corr, double* cum,
+                            double* smu, double* skap, int threads) {
+    if (M < 1 || d < 1 || d > KMAX || d > M || rank0 < 0 || count < 0 ||
+        rank0 + count > binom(M, d))
+        return 1;
+    init_parts();
+    oracle_threads(threads);
+    double* Q = make_q(sigma, M);
+    if (!Q) return 3;
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(| : err)
+    for (int64_t i = 0; i < count; ++i) {
+        int S[KMAX];
+        unrank(d, rank0 + i, S);
+        err |= subset_values(Q, mu, M, S, d, convention, &corr[i], &cum[i], smu ? &smu[i] : NULL,
+                             skap ? &skap[i] : NULL);
+    }
+    free(Q);
+    return err;
+}
+
+/* Summand magnitudes (see subset_values) of the sampled order-d subsets: the
+ * scales of the stated FP64 tolerances. */
+int oracle_tolerance_scale_mu(int M, const double* sigma, const double* mu, int d,
+                              const int64_t* ranks, int64_t n, int convention, double* smu,
+                              double* skap, int threads) {
+    if (M < 1 || d < 1 || d > KMAX || d > M) return 1;
+    init_parts();
+    oracle_threads(threads);
+    double* Q = make_q(sigma, M);
+    if (!Q) return 3;
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(| : err)
+    for (int64_t i = 0; i < n; ++i) {
+        int S[KMAX];
+        double c, k;
+        unrank(d, ranks[i], S);
+        err |= subset_values(Q, mu, M, S, d, convention, &c, &k, &smu[i], &skap[i]);
+    }
+    free(Q);
+    return err;
 }
 
 /* inverse of the SPD matrix Q_T (n x n) by Gauss-Jordan without pivoting */
@@ -311,7 +371,7 @@ int oracle_loss_grad(int M, const double* sigma, int K, const double* target, do
             double c, k;
             double pv;
             err |= vacuum_prob(Q, NULL, M, S, d, (1u << d) - 1, &pv);
-            err |= subset_values(Q, NULL, M, S, d, 0, &c, &k);
+            err |= subset_values(Q, NULL, M, S, d, 0, &c, &k, NULL, NULL);
             p[off[d] + r] = pv;
             mu[off[d] + r] = c;
             kap[off[d] + r] = k;

@@ -151,6 +151,55 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+# The C ABI receives bare pointers and cannot see buffer sizes, so every size,
+# dtype and device is checked here, before the call: an undersized buffer would
+# otherwise be read or written out of bounds by the kernels.
+
+def _need(t, name, numel, dtype=torch.float64, shape=None, optional=False):
+    """Check that t is a contiguous tensor of `dtype` with `numel` elements (and
+    `shape` if given); None is accepted when optional."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: {dtype} tensor required, got {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: {numel} elements required, got {t.numel()}")
+    if shape is not None and tuple(t.shape) not in (tuple(shape), (numel,)):
+        raise ValueError(f"{name}: shape {tuple(shape)} required, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: contiguous tensor required")
+
+
+def _same_device(*named):
+    """All given tensors (None skipped) on one GPU."""
+    dev = None
+    for name, t in named:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError(f"{name}: device tensor required")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError(f"{name} is on {t.device}, expected {dev}")
+
+
+def _outputs(M, max_order):
+    """N(M, K), or ValueError for arguments the library would reject anyway."""
+    n = gbs_total_outputs(M, max_order)
+    if n < 0:
+        raise ValueError(f"invalid M = {M} / max_order = {max_order}")
+    return n
+
+
+def _sigma(M, sigma, name="sigma"):
+    _need(sigma, name, 4 * M * M, shape=(2 * M, 2 * M))
+
+
 def _stream(stream, device):
     if stream is None:
         return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
@@ -214,8 +263,11 @@ def _out(buf, n, like):
 
 def gbs_correlators(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0, corr=None,
                     stream=None) -> torch.Tensor:
-    n = gbs_total_outputs(M, max_order)
-    corr = _out(corr, max(n, 0), sigma)
+    n = _outputs(M, max_order)
+    _sigma(M, sigma)
+    corr = _out(corr, n, sigma)
+    _need(corr, "corr", n)
+    _same_device(("sigma", sigma), ("corr", corr))
     with torch.cuda.device(sigma.device):
         st = lib().gbs_correlators(M, _ptr(sigma), max_order, flags, _ptr(corr),
                                    _stream(stream, sigma.device))
@@ -225,10 +277,14 @@ def gbs_correlators(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0,
 
 def gbs_cumulants(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0, corr=None, cum=None,
                   stream=None, want_corr: bool = True) -> tuple:
-    n = gbs_total_outputs(M, max_order)
+    n = _outputs(M, max_order)
+    _sigma(M, sigma)
     if want_corr:
-        corr = _out(corr, max(n, 0), sigma)
-    cum = _out(cum, max(n, 0), sigma)
+        corr = _out(corr, n, sigma)
+    cum = _out(cum, n, sigma)
+    _need(corr, "corr", n, optional=True)
+    _need(cum, "cum", n)
+    _same_device(("sigma", sigma), ("corr", corr), ("cum", cum))
     with torch.cuda.device(sigma.device):
         st = lib().gbs_cumulants(M, _ptr(sigma), max_order, flags, _ptr(corr), _ptr(cum),
                                  _stream(stream, sigma.device))
@@ -239,10 +295,15 @@ def gbs_cumulants(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0, c
 def gbs_cumulants_displaced(M: int, sigma: torch.Tensor, mu: torch.Tensor, max_order: int,
                             flags: int = 0, corr=None, cum=None, stream=None,
                             want_corr: bool = True) -> tuple:
-    n = gbs_total_outputs(M, max_order)
+    n = _outputs(M, max_order)
+    _sigma(M, sigma)
+    _need(mu, "mu", 2 * M)
     if want_corr:
-        corr = _out(corr, max(n, 0), sigma)
-    cum = _out(cum, max(n, 0), sigma)
+        corr = _out(corr, n, sigma)
+    cum = _out(cum, n, sigma)
+    _need(corr, "corr", n, optional=True)
+    _need(cum, "cum", n)
+    _same_device(("sigma", sigma), ("mu", mu), ("corr", corr), ("cum", cum))
     with torch.cuda.device(sigma.device):
         st = lib().gbs_cumulants_displaced(M, _ptr(sigma), _ptr(mu), max_order, flags, _ptr(corr),
                                            _ptr(cum), _stream(stream, sigma.device))
@@ -253,9 +314,17 @@ def gbs_cumulants_displaced(M: int, sigma: torch.Tensor, mu: torch.Tensor, max_o
 def gbs_cumulants_shard(M: int, sigma: torch.Tensor, order: int, rank0: int, count: int,
                         flags: int = 0, corr=None, cum=None, stream=None,
                         want_corr: bool = True) -> tuple:
+    if not (1 <= M <= GBS_MAX_MODES and 1 <= order <= min(GBS_MAX_ORDER, M)):
+        raise ValueError(f"invalid M = {M} / order = {order}")
+    if rank0 < 0 or count < 0 or rank0 + count > gbs_num_subsets(M, order):
+        raise ValueError(f"rank range [{rank0}, {rank0} + {count}) outside C({M}, {order})")
+    _sigma(M, sigma)
     if want_corr:
         corr = _out(corr, count, sigma)
     cum = _out(cum, count, sigma)
+    _need(corr, "corr", count, optional=True)
+    _need(cum, "cum", count, optional=True)
+    _same_device(("sigma", sigma), ("corr", corr), ("cum", cum))
     with torch.cuda.device(sigma.device):
         st = lib().gbs_cumulants_shard(M, _ptr(sigma), order, rank0, count, flags, _ptr(corr),
                                        _ptr(cum), _stream(stream, sigma.device))
@@ -275,7 +344,18 @@ def gbs_sample(M: int, kappa: torch.Tensor, max_order: int, uniforms: torch.Tens
                want_prob: bool = True, want_cond: bool = False) -> tuple:
     """Sampler: uniforms is (M, n) FP64; returns (bits (n, M) uint8, prob (n,) or
     None, cond (M, n) or None)."""
-    n = uniforms.shape[1] if uniforms.dim() == 2 else uniforms.numel() // M
+    if M < 1:
+        raise ValueError(f"invalid M = {M}")
+    if uniforms.dim() == 2:
+        if uniforms.shape[0] != M:
+            raise ValueError(f"uniforms: shape ({M}, n) required, got {tuple(uniforms.shape)}")
+        n = uniforms.shape[1]
+    else:
+        if uniforms.numel() % M:
+            raise ValueError(f"uniforms: a multiple of M = {M} elements required")
+        n = uniforms.numel() // M
+    _need(kappa, "kappa", _outputs(M, max_order))
+    _need(uniforms, "uniforms", M * n)
     dev = kappa.device
     if bits is None:
         bits = torch.empty((n, M), dtype=torch.uint8, device=dev)
@@ -283,6 +363,11 @@ def gbs_sample(M: int, kappa: torch.Tensor, max_order: int, uniforms: torch.Tens
         prob = torch.empty(n, dtype=torch.float64, device=dev)
     if cond is None and want_cond:
         cond = torch.empty((M, n), dtype=torch.float64, device=dev)
+    _need(bits, "bits", n * M, dtype=torch.uint8)
+    _need(prob, "prob", n, optional=True)
+    _need(cond, "cond", M * n, optional=True)
+    _same_device(("kappa", kappa), ("uniforms", uniforms), ("bits", bits), ("prob", prob),
+                 ("cond", cond))
     with torch.cuda.device(dev):
         st = lib().gbs_sample(M, _ptr(kappa), max_order, n, _ptr(uniforms), _ptr_u8(bits),
                               _ptr(prob), _ptr(cond), batch, flags, _stream(stream, dev))
@@ -293,8 +378,14 @@ def gbs_sample(M: int, kappa: torch.Tensor, max_order: int, uniforms: torch.Tens
 def gbs_sample_cumulants(bits: torch.Tensor, max_order: int, cum=None, flags: int = 0,
                          stream=None) -> torch.Tensor:
     """Unbiased click cumulants of orders 1..max_order from samples (n, M) uint8."""
+    if bits.dim() != 2:
+        raise ValueError("bits: shape (nsamples, M) required")
     n, M = bits.shape
-    cum = _out(cum, max(gbs_total_outputs(M, max_order), 0), bits)
+    _need(bits, "bits", n * M, dtype=torch.uint8)
+    nout = _outputs(M, max_order)
+    cum = _out(cum, nout, bits)
+    _need(cum, "cum", nout)
+    _same_device(("bits", bits), ("cum", cum))
     with torch.cuda.device(bits.device):
         st = lib().gbs_sample_cumulants(M, n, _ptr_u8(bits), max_order, _ptr(cum), flags,
                                         _stream(stream, bits.device))
@@ -304,8 +395,12 @@ def gbs_sample_cumulants(bits: torch.Tensor, max_order: int, cum=None, flags: in
 
 def gbs_pearson(x: torch.Tensor, y: torch.Tensor, r=None, flags: int = 0, stream=None) -> torch.Tensor:
     """Pearson coefficient of two device FP64 vectors (a one-element tensor)."""
+    _need(x, "x", x.numel() if isinstance(x, torch.Tensor) else -1)
+    _need(y, "y", x.numel())
     if r is None:
         r = torch.empty(1, dtype=torch.float64, device=x.device)
+    _need(r, "r", 1)
+    _same_device(("x", x), ("y", y), ("r", r))
     with torch.cuda.device(x.device):
         st = lib().gbs_pearson(x.numel(), _ptr(x), _ptr(y), _ptr(r), flags, _stream(stream, x.device))
     _check(st, "gbs_pearson")
@@ -314,8 +409,15 @@ def gbs_pearson(x: torch.Tensor, y: torch.Tensor, r=None, flags: int = 0, stream
 
 def gbs_cumulant_grad(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0,
                       grad_corr=None, grad_cum=None, grad_sigma=None, stream=None) -> torch.Tensor:
+    n = _outputs(M, max_order)
+    _sigma(M, sigma)
+    _need(grad_corr, "grad_corr", n, optional=True)
+    _need(grad_cum, "grad_cum", n, optional=True)
     if grad_sigma is None:
         grad_sigma = torch.empty_like(sigma)
+    _sigma(M, grad_sigma, "grad_sigma")
+    _same_device(("sigma", sigma), ("grad_corr", grad_corr), ("grad_cum", grad_cum),
+                 ("grad_sigma", grad_sigma))
     with torch.cuda.device(sigma.device):
         st = lib().gbs_cumulant_grad(M, _ptr(sigma), max_order, flags, _ptr(grad_corr),
                                      _ptr(grad_cum), _ptr(grad_sigma), _stream(stream, sigma.device))
@@ -323,7 +425,17 @@ def gbs_cumulant_grad(M: int, sigma: torch.Tensor, max_order: int, flags: int = 
     return grad_sigma
 
 
-def _instances(instances):
+def _instances(instances, max_order):
+    if len(instances) == 0:
+        raise ValueError("at least one instance is required")
+    for i, (M, sigma, corr, cum) in enumerate(instances):
+        n = _outputs(M, max_order)
+        _sigma(M, sigma, f"instance {i} sigma")
+        _need(corr, f"instance {i} corr", n, optional=True)
+        _need(cum, f"instance {i} cum", n)
+    for i, (M, sigma, corr, cum) in enumerate(instances):
+        _same_device(("instance 0 sigma", instances[0][1]), (f"instance {i} sigma", sigma),
+                     (f"instance {i} corr", corr), (f"instance {i} cum", cum))
     arr = (gbs_instance * len(instances))()
     for i, (M, sigma, corr, cum) in enumerate(instances):
         arr[i].M = M
@@ -336,7 +448,7 @@ def _instances(instances):
 
 def gbs_cumulants_batched(instances, max_order: int, flags: int = 0, stream=None) -> None:
     """instances: list of (M, sigma, corr or None, cum) with device tensors."""
-    arr = _instances(instances)
+    arr = _instances(instances, max_order)
     dev = instances[0][1].device
     with torch.cuda.device(dev):
         st = lib().gbs_cumulants_batched(len(instances), arr, max_order, flags, _stream(stream, dev))
@@ -344,7 +456,7 @@ def gbs_cumulants_batched(instances, max_order: int, flags: int = 0, stream=None
 
 
 def gbs_autotune_batched(instances, max_order: int, flags: int = 0, stream=None) -> dict:
-    arr = _instances(instances)
+    arr = _instances(instances, max_order)
     dev = instances[0][1].device
     best = gbs_tuning()
     with torch.cuda.device(dev):

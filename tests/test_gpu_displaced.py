@@ -9,7 +9,7 @@ import pytest
 
 import gbs_inputs as G
 import oracle as O
-from parity import assert_within, fp64_tolerance
+from parity import assert_within, fp64_scales, fp64_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -48,9 +48,9 @@ def _check_full(P, sigma, mu, K, conv, flags_extra=0, what=""):
     for d in range(1, K + 1):
         a, b = O.order_offset(M, d), O.order_offset(M, d + 1)
         ranks = np.arange(b - a, dtype=np.int64)
-        vmu, vkap = O.c_error_floor(sigma, d, ranks, conv, mu=mu)
-        assert_within(corr[a:b], rc[a:b], fp64_tolerance(rc[a:b], vmu), f"{what} corr d={d}")
-        assert_within(cum[a:b], rk[a:b], fp64_tolerance(rk[a:b], vkap), f"{what} cum d={d}")
+        smu, skap = fp64_scales(sigma, d, ranks, conv, mu=mu)
+        assert_within(corr[a:b], rc[a:b], fp64_tolerance(rc[a:b], smu), f"{what} corr d={d}")
+        assert_within(cum[a:b], rk[a:b], fp64_tolerance(rk[a:b], skap), f"{what} cum d={d}")
     return corr, cum
 
 
@@ -95,9 +95,9 @@ def _check_sampled(P, sigma, mu, K, picks, conv, what):
         idx = torch.from_numpy(O.order_offset(M, d) + ranks).to("cuda:0")
         gc, gk = corr[idx].cpu().numpy(), cum[idx].cpu().numpy()
         rc, rk = O.c_forward_sample(sigma, d, ranks, conv, mu=mu)
-        vmu, vkap = O.c_error_floor(sigma, d, ranks, conv, mu=mu)
-        assert_within(gc, rc, fp64_tolerance(rc, vmu), f"{what} corr d={d}")
-        assert_within(gk, rk, fp64_tolerance(rk, vkap), f"{what} cum d={d}")
+        smu, skap = fp64_scales(sigma, d, ranks, conv, mu=mu)
+        assert_within(gc, rc, fp64_tolerance(rc, smu), f"{what} corr d={d}")
+        assert_within(gk, rk, fp64_tolerance(rk, skap), f"{what} cum d={d}")
 
 
 @pytest.mark.parametrize("conv", [0, 1], ids=["click", "parity"])
@@ -150,9 +150,9 @@ def test_zero_mean_matches_undisplaced(P):
     c0, k0, c1, k1 = (x.cpu().numpy() for x in (c0, k0, c1, k1))
     for d in range(1, 5):
         a, b = O.order_offset(30, d), O.order_offset(30, d + 1)
-        vmu, vkap = O.c_error_floor(inst.sigma, d, np.arange(b - a, dtype=np.int64))
-        assert_within(c1[a:b], c0[a:b], 2 * fp64_tolerance(c0[a:b], vmu), f"corr d={d}")
-        assert_within(k1[a:b], k0[a:b], 2 * fp64_tolerance(k0[a:b], vkap), f"cum d={d}")
+        smu, skap = fp64_scales(inst.sigma, d, np.arange(b - a, dtype=np.int64))
+        assert_within(c1[a:b], c0[a:b], 2 * fp64_tolerance(c0[a:b], smu), f"corr d={d}")
+        assert_within(k1[a:b], k0[a:b], 2 * fp64_tolerance(k0[a:b], skap), f"cum d={d}")
 
 
 def test_coherent_product_state_closed_form(P):

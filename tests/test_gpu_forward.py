@@ -9,7 +9,7 @@ import pytest
 
 import gbs_inputs as G
 import oracle as O
-from parity import assert_within, fp64_tolerance, rel_stats
+from parity import assert_within, fp64_scales, fp64_tolerance, rel_stats
 
 pytestmark = pytest.mark.gpu
 
@@ -46,9 +46,9 @@ def _check_full(P, sigma, K, conv, flags_extra=0, what=""):
     for d in range(1, K + 1):
         a, b = O.order_offset(M, d), O.order_offset(M, d + 1)
         ranks = np.arange(b - a, dtype=np.int64)
-        vmu, vkap = O.c_error_floor(sigma, d, ranks, conv)
-        assert_within(corr[a:b], rc[a:b], fp64_tolerance(rc[a:b], vmu), f"{what} corr d={d}")
-        assert_within(cum[a:b], rk[a:b], fp64_tolerance(rk[a:b], vkap), f"{what} cum d={d}")
+        smu, skap = fp64_scales(sigma, d, ranks, conv)
+        assert_within(corr[a:b], rc[a:b], fp64_tolerance(rc[a:b], smu), f"{what} corr d={d}")
+        assert_within(cum[a:b], rk[a:b], fp64_tolerance(rk[a:b], skap), f"{what} cum d={d}")
     return corr, cum
 
 
@@ -60,9 +60,9 @@ def test_m16_k3_against_golden(P, conv):
     corr, cum = _run(P, g["sigma"], 3, conv)
     for d in (1, 2, 3):
         a, b = O.order_offset(16, d), O.order_offset(16, d + 1)
-        vmu, vkap = O.c_error_floor(g["sigma"], d, np.arange(b - a, dtype=np.int64), conv)
-        assert_within(corr[a:b], g["corr"][a:b], fp64_tolerance(g["corr"][a:b], vmu), f"corr d={d}")
-        assert_within(cum[a:b], g["cum"][a:b], fp64_tolerance(g["cum"][a:b], vkap), f"cum d={d}")
+        smu, skap = fp64_scales(g["sigma"], d, np.arange(b - a, dtype=np.int64), conv)
+        assert_within(corr[a:b], g["corr"][a:b], fp64_tolerance(g["corr"][a:b], smu), f"corr d={d}")
+        assert_within(cum[a:b], g["cum"][a:b], fp64_tolerance(g["cum"][a:b], skap), f"cum d={d}")
 
 
 KERNELS = [0, 16]  # order-recursive (default), GBS_ALL_MINORS
@@ -99,21 +99,21 @@ def test_m144_k5_sampled(P, kernel):
         n = math.comb(144, d)
         ranks = np.arange(n, dtype=np.int64) if d <= 3 else G.random_ranks(n, 20000, seed=100 + d)
         rc, rk = O.c_forward_sample(inst.sigma, d, ranks)
-        vmu, vkap = O.c_error_floor(inst.sigma, d, ranks)
+        smu, skap = fp64_scales(inst.sigma, d, ranks)
         off = O.order_offset(144, d)
-        assert_within(corr[off + ranks], rc, fp64_tolerance(rc, vmu), f"M=144 corr d={d}")
-        assert_within(cum[off + ranks], rk, fp64_tolerance(rk, vkap), f"M=144 cum d={d}")
+        assert_within(corr[off + ranks], rc, fp64_tolerance(rc, smu), f"M=144 corr d={d}")
+        assert_within(cum[off + ranks], rk, fp64_tolerance(rk, skap), f"M=144 cum d={d}")
         if d == 5:
             _say("order 5 corr rel", rel_stats(corr[off + ranks], rc))
-            _say("order 5 cum |delta|/vkap max",
-                 float(np.max(np.abs(cum[off + ranks] - rk) / vkap)))
+            _say("order 5 cum |delta|/tol max",
+                 float(np.max(np.abs(cum[off + ranks] - rk) / fp64_tolerance(rk, skap))))
     # the last outputs of the layout (ragged tail of the order-5 launch)
     tail = np.arange(math.comb(144, 5) - 300, math.comb(144, 5), dtype=np.int64)
     rc, rk = O.c_forward_sample(inst.sigma, 5, tail)
-    vmu, vkap = O.c_error_floor(inst.sigma, 5, tail)
+    smu, skap = fp64_scales(inst.sigma, 5, tail)
     off = O.order_offset(144, 5)
-    assert_within(corr[off + tail], rc, fp64_tolerance(rc, vmu), "tail corr")
-    assert_within(cum[off + tail], rk, fp64_tolerance(rk, vkap), "tail cum")
+    assert_within(corr[off + tail], rc, fp64_tolerance(rc, smu), "tail corr")
+    assert_within(cum[off + tail], rk, fp64_tolerance(rk, skap), "tail cum")
 
 
 def _run_sampled(P, sigma, K, picks, flags=0):
@@ -153,9 +153,9 @@ def test_tile_kernel_range(P, conv):
     got = _run_sampled(P, inst.sigma, K, picks, conv)
     for d, ranks in picks.items():
         rc, rk = O.c_forward_sample(inst.sigma, d, ranks, conv)
-        vmu, vkap = O.c_error_floor(inst.sigma, d, ranks, conv)
-        assert_within(got[d][0], rc, fp64_tolerance(rc, vmu), f"M=160 corr d={d}")
-        assert_within(got[d][1], rk, fp64_tolerance(rk, vkap), f"M=160 cum d={d}")
+        smu, skap = fp64_scales(inst.sigma, d, ranks, conv)
+        assert_within(got[d][0], rc, fp64_tolerance(rc, smu), f"M=160 corr d={d}")
+        assert_within(got[d][1], rk, fp64_tolerance(rk, skap), f"M=160 cum d={d}")
 
 
 def test_rec_kernel_64bit_ranks(P):
@@ -168,9 +168,9 @@ def test_rec_kernel_64bit_ranks(P):
     got = _run_sampled(P, inst.sigma, K, picks)
     for d, ranks in picks.items():
         rc, rk = O.c_forward_sample(inst.sigma, d, ranks)
-        vmu, vkap = O.c_error_floor(inst.sigma, d, ranks)
-        assert_within(got[d][0], rc, fp64_tolerance(rc, vmu), f"M=1500 corr d={d}")
-        assert_within(got[d][1], rk, fp64_tolerance(rk, vkap), f"M=1500 cum d={d}")
+        smu, skap = fp64_scales(inst.sigma, d, ranks)
+        assert_within(got[d][0], rc, fp64_tolerance(rc, smu), f"M=1500 corr d={d}")
+        assert_within(got[d][1], rk, fp64_tolerance(rk, skap), f"M=1500 cum d={d}")
 
 
 def test_python_oracle_direct(P):
@@ -208,10 +208,10 @@ def test_max_modes(P):
         n = math.comb(M, d)
         ranks = G.random_ranks(n, 5000, seed=d)
         rc, rk = O.c_forward_sample(sigma, d, ranks)
-        vmu, vkap = O.c_error_floor(sigma, d, ranks)
+        smu, skap = fp64_scales(sigma, d, ranks)
         off = O.order_offset(M, d)
-        assert_within(corr[off + ranks], rc, fp64_tolerance(rc, vmu), f"max corr d={d}")
-        assert_within(cum[off + ranks], rk, fp64_tolerance(rk, vkap), f"max cum d={d}")
+        assert_within(corr[off + ranks], rc, fp64_tolerance(rc, smu), f"max corr d={d}")
+        assert_within(cum[off + ranks], rk, fp64_tolerance(rk, skap), f"max cum d={d}")
 
 
 def test_vacuum_and_product_state(P):
@@ -263,6 +263,50 @@ def test_mixed_error_bound(P, kernel):
         ek = float(np.abs(cum[a:b] - rk[a:b]).max() / np.abs(rk[a:b]).max())
         _say(f"mixed order {d}: corr normwise {ec:.2e}  cum normwise {ek:.2e}")
         assert ec <= MIXED_BOUND_CORR[d] and ek <= MIXED_BOUND_CUM[d]
+
+
+# Stated bound of the mixed form at the M = 144, K = 5 workload (the benchmark's
+# launch), per order (index = order), against the FP64 oracle on sampled
+# subsets: normwise max|delta| / max|ref|, and the 99th percentile of the
+# elementwise relative error of the cumulants.  About three times the values
+# measured over every output.
+MIXED144_NORM_CORR = [0, 1e-13, 3e-8, 1e-7, 4e-7, 1.5e-6]
+MIXED144_NORM_CUM = [0, 1e-13, 6e-7, 2e-5, 2e-4, 3e-3]
+MIXED144_P99_CUM = [0, 1e-13, 1e-6, 2e-3, 5e-2, 1.0]
+
+
+def mixed_errors(got_c, got_k, rc, rk):
+    """Normwise errors of correlators and cumulants and the elementwise
+    relative-error statistics of the cumulants."""
+    ec = float(np.abs(got_c - rc).max() / np.abs(rc).max())
+    ek = float(np.abs(got_k - rk).max() / np.abs(rk).max())
+    return ec, ek, rel_stats(got_k, rk), rel_stats(got_c, rc)
+
+
+def test_mixed_m144_k5_sampled(P):
+    """The mixed form at the M = 144, K = 5 workload against the FP64 oracle:
+    every output of orders 1-2, 20,000 sampled outputs of orders 3-5 and the
+    last 300 ranks of each order."""
+    _say("case: mixed M=144 K=5 sampled")
+    inst = G.make_instance("m144_k5")
+    corr, cum = _run(P, inst.sigma, 5, P.GBS_MIXED)
+    for d in range(1, 6):
+        n = math.comb(144, d)
+        if d <= 2:
+            ranks = np.arange(n, dtype=np.int64)
+        else:
+            ranks = np.unique(np.concatenate([G.random_ranks(n, 20000, seed=400 + d),
+                                              np.arange(n - 300, n, dtype=np.int64)]))
+        rc, rk = O.c_forward_sample(inst.sigma, d, ranks)
+        off = O.order_offset(144, d)
+        ec, ek, sk, sc = mixed_errors(corr[off + ranks], cum[off + ranks], rc, rk)
+        _say(f"mixed M=144 order {d}: corr normwise {ec:.2e} (rel p99 {sc['p99']:.2e}), "
+             f"cum normwise {ek:.2e}, cum rel median {sk['median']:.2e} p99 {sk['p99']:.2e} "
+             f"max {sk['max']:.2e}")
+        assert np.all(np.isfinite(corr[off + ranks])) and np.all(np.isfinite(cum[off + ranks]))
+        assert ec <= MIXED144_NORM_CORR[d], (d, ec)
+        assert ek <= MIXED144_NORM_CUM[d], (d, ek)
+        assert sk["p99"] <= MIXED144_P99_CUM[d], (d, sk)
 
 
 def test_deterministic(P):

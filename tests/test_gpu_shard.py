@@ -9,7 +9,7 @@ import pytest
 
 import gbs_inputs as G
 import oracle as O
-from parity import assert_within, fp64_tolerance
+from parity import assert_within, fp64_scales, fp64_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -55,17 +55,17 @@ def test_shard_is_a_slice_of_the_full_pass(P, conv):
         torch.cuda.synchronize()
         # two FP64 evaluations: each within the oracle tolerance of the exact value
         ranks = np.arange(r0, r0 + cnt, dtype=np.int64)
-        vmu, vkap = O.c_error_floor(inst.sigma, 5, ranks, conv)
+        smu, skap = fp64_scales(inst.sigma, 5, ranks, conv)
         cd = c_def[off + r0:off + r0 + cnt].cpu().numpy()
         kd = k_def[off + r0:off + r0 + cnt].cpu().numpy()
-        assert_within(c.cpu().numpy(), cd, 2 * fp64_tolerance(cd, vmu), f"corr [{r0}, +{cnt})")
-        assert_within(k.cpu().numpy(), kd, 2 * fp64_tolerance(kd, vkap), f"cum [{r0}, +{cnt})")
+        assert_within(c.cpu().numpy(), cd, 2 * fp64_tolerance(cd, smu), f"corr [{r0}, +{cnt})")
+        assert_within(k.cpu().numpy(), kd, 2 * fp64_tolerance(kd, skap), f"cum [{r0}, +{cnt})")
     ranks = np.arange(123_457, 123_457 + 2000, dtype=np.int64)
     c, k = P.gbs_cumulants_shard(40, s, 5, 123_457, 2000, conv)
     rc, rk = O.c_forward_sample(inst.sigma, 5, ranks, conv)
-    vmu, vkap = O.c_error_floor(inst.sigma, 5, ranks, conv)
-    assert_within(c.cpu().numpy(), rc, fp64_tolerance(rc, vmu), "M=40 corr")
-    assert_within(k.cpu().numpy(), rk, fp64_tolerance(rk, vkap), "M=40 cum")
+    smu, skap = fp64_scales(inst.sigma, 5, ranks, conv)
+    assert_within(c.cpu().numpy(), rc, fp64_tolerance(rc, smu), "M=40 corr")
+    assert_within(k.cpu().numpy(), rk, fp64_tolerance(rk, skap), "M=40 cum")
 
 
 @pytest.mark.parametrize("conv", [0, 1], ids=["click", "parity"])
@@ -80,10 +80,10 @@ def test_shard_every_rank_small(P, order, conv):
     n = math.comb(13, order)
     ranks = np.arange(n, dtype=np.int64)
     rc, rk = O.c_forward_sample(inst.sigma, order, ranks, conv)
-    vmu, vkap = O.c_error_floor(inst.sigma, order, ranks, conv)
+    smu, skap = fp64_scales(inst.sigma, order, ranks, conv)
     c, k = P.gbs_cumulants_shard(13, s, order, 0, n, conv)
-    assert_within(c.cpu().numpy(), rc, fp64_tolerance(rc, vmu), f"d={order} corr")
-    assert_within(k.cpu().numpy(), rk, fp64_tolerance(rk, vkap), f"d={order} cum")
+    assert_within(c.cpu().numpy(), rc, fp64_tolerance(rc, smu), f"d={order} corr")
+    assert_within(k.cpu().numpy(), rk, fp64_tolerance(rk, skap), f"d={order} cum")
     cuts = [0, 1, 2, 7, 30, n // 2, n // 2 + 1, n - 3, n]
     for a, b in zip(cuts[:-1], cuts[1:]):
         if b <= a:
@@ -118,6 +118,6 @@ def test_pseudo_pnr_m1152(P, pnr, order, where):
                                       np.arange(0, 50)]))
     ranks = r0 + local
     rc, rk = O.c_forward_sample(pnr, order, ranks)
-    vmu, vkap = O.c_error_floor(pnr, order, ranks)
-    assert_within(c.cpu().numpy()[local], rc, fp64_tolerance(rc, vmu), f"M=1152 d={order} corr")
-    assert_within(k.cpu().numpy()[local], rk, fp64_tolerance(rk, vkap), f"M=1152 d={order} cum")
+    smu, skap = fp64_scales(pnr, order, ranks)
+    assert_within(c.cpu().numpy()[local], rc, fp64_tolerance(rc, smu), f"M=1152 d={order} corr")
+    assert_within(k.cpu().numpy()[local], rk, fp64_tolerance(rk, skap), f"M=1152 d={order} cum")
