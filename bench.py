@@ -135,11 +135,15 @@ def precision_errors(torch, P, corr64, cum64, corrmx, cummx):
     return out
 
 
-def fp64_tolerance(np, ref, scale):
-    """The FP64 parity tolerance of the click convention: 1e-10 max(|ref|,
-    1e-4 scale), scale the summand magnitude of the sum that gives the output
-    (oracle.c_tolerance_scale)."""
-    return 1e-10 * np.maximum(np.abs(ref), 1e-4 * scale)
+def fp64_tolerance(np, ref, scale, carried=None):
+    """The FP64 parity tolerance: 1e-10 max(|ref|, 1e-4 scale), scale the
+    summand magnitude of the sum that gives the output
+    (oracle.c_tolerance_scale), plus, for a cumulant, 4 u times the rounding
+    its correlators carry in (oracle.c_error_floor)."""
+    tol = 1e-10 * np.maximum(np.abs(ref), 1e-4 * scale)
+    if carried is not None:
+        tol = tol + 4.0 * 2.0 ** -53 * carried
+    return tol
 
 
 def fp64_parity_sample(np, O, G, inst, corr, cum, n=3000, mu=None):
@@ -151,11 +155,12 @@ def fp64_parity_sample(np, O, G, inst, corr, cum, n=3000, mu=None):
         ranks = G.random_ranks(cnt, min(n, cnt), seed=900 + d)
         rc, rk = O.c_forward_sample(inst.sigma, d, ranks, mu=mu)
         smu, skap = O.c_tolerance_scale(inst.sigma, d, ranks, mu=mu)
+        _, vk = O.c_error_floor(inst.sigma, d, ranks, mu=mu)
         off = O.order_offset(M, d)
         gc = corr[off + ranks]
         gk = cum[off + ranks]
-        for got, ref, v in ((gc, rc, smu), (gk, rk, skap)):
-            worst = max(worst, float(np.max(np.abs(got - ref) / fp64_tolerance(np, ref, v))))
+        for got, ref, v, c in ((gc, rc, smu, None), (gk, rk, skap, vk)):
+            worst = max(worst, float(np.max(np.abs(got - ref) / fp64_tolerance(np, ref, v, c))))
     return worst
 
 

@@ -3,13 +3,17 @@ evaluation of the same definitions.
 
 At the M = 144, K = 5 workload, for every order and both conventions, on
 sampled subsets:
-* the FP64 oracle's own error against the 40-digit arbiter stays inside the
-  stated tolerance 1e-10 max(|ref|, 1e-4 scale), with room for a second FP64
-  evaluation (the GPU path) rounding the other way;
-* the floor is not inflated: 1e-14 scale is at most FLOOR_SLACK times the
-  largest error the arbiter measures, per order (the error floor used before,
-  64 u times the propagated magnitude of every cancelling term, was about
-  6,000 times the measured error of the order-5 click cumulants and fails this);
+* the FP64 oracle's own error against the 40-digit arbiter stays inside half
+  of the stated tolerance 1e-10 max(|ref|, 1e-4 S_pi) + 4 u V, leaving the
+  other half for a second FP64 evaluation (the GPU path) rounding the other
+  way;
+* the tolerance is not inflated: its median is at most SLACK times the largest
+  error the arbiter measures, per order (the error floor used before, 64 u V
+  alone, was about 6,000 times the measured error of the order-5 click
+  cumulants and fails this);
+* for weakly illuminated modes (click probabilities of a few percent) the
+  partition-sum term alone is not a valid bound: the FP64 oracle misses it,
+  and the carried-in term 4 u V restores it;
 * the scales the C oracle reports equal the Python tier's.
 """
 import numpy as np
@@ -22,7 +26,7 @@ from parity import fp64_scales, fp64_tolerance
 pytestmark = pytest.mark.skipif(not O.c_oracle_available(), reason="C oracle not built")
 
 U = 2.0 ** -53
-FLOOR_SLACK = 400.0
+SLACK = 1000.0
 NSAMPLE = 16
 
 
@@ -48,10 +52,9 @@ def test_tolerance_against_arbiter(inst, conv, d):
     # one FP64 evaluation uses at most half of the tolerance
     assert np.all(ec <= 0.5 * tc), (ec / tc).max()
     assert np.all(ek <= 0.5 * tk), (ek / tk).max()
-    # the cumulant floor stays within FLOOR_SLACK of the measured error
-    floor = 1e-14 * skap
+    # the cumulant tolerance stays within SLACK of the measured error
     assert ek.max() > 0.0
-    assert np.median(floor) <= FLOOR_SLACK * ek.max(), (np.median(floor), ek.max())
+    assert np.median(tk) <= SLACK * ek.max(), (np.median(tk), ek.max())
 
 
 def test_old_floor_fails_the_slack_pin(inst):
@@ -63,7 +66,37 @@ def test_old_floor_fails_the_slack_pin(inst):
     _, vkap = O.c_error_floor(inst.sigma, d, ranks)
     arb = _arbiter(inst.sigma, d, ranks, O.CLICK)
     ek = np.abs(rk - arb[:, 1])
-    assert np.median(64 * U * vkap) > FLOOR_SLACK * ek.max()
+    assert np.median(64 * U * vkap) > SLACK * ek.max()
+
+
+def _weak_light(M, seed=1):
+    """Independent lossy squeezed modes with click probabilities of a few
+    percent, coupled by a weak random symmetric perturbation (Q stays SPD)."""
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.3, 1.0, M)
+    eta = rng.uniform(0.3, 0.6, M)
+    sigma = G.product_state_covariance(r, eta)
+    B = rng.standard_normal((2 * M, 2 * M)) * 5e-4
+    return sigma + 0.5 * (B + B.T)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_weak_light_needs_the_carried_term(d):
+    """Cumulants of weakly illuminated modes are high-order differences of
+    probabilities near one: the rounding of the correlators dominates, so the
+    partition-sum bound alone is missed by the FP64 oracle itself, while the
+    full tolerance holds with room for the second evaluation."""
+    M = 64
+    sigma = _weak_light(M)
+    ranks = G.random_ranks(O.num_subsets(M, d), 40, seed=7300 + d)
+    _, rk = O.c_forward_sample(sigma, d, ranks)
+    _, skap = fp64_scales(sigma, d, ranks)
+    arb = _arbiter(sigma, d, ranks, O.CLICK)
+    ek = np.abs(rk - arb[:, 1])
+    partition_only = 1e-10 * np.maximum(np.abs(arb[:, 1]), 1e-4 * skap[0])
+    assert np.any(ek > partition_only), (ek / partition_only).max()
+    assert np.all(ek <= 0.5 * fp64_tolerance(arb[:, 1], skap)), \
+        (ek / fp64_tolerance(arb[:, 1], skap)).max()
 
 
 def test_displaced_tolerance_against_arbiter(inst):
