@@ -1,16 +1,21 @@
-"""Compile libgbs.so for gfx950 with hipcc (in-tree)."""
+"""Compile libgbs.so for gfx950 with hipcc (in-tree).
+
+Every HIP source is compiled to its own object in parallel (each carries its
+own device code), then the objects are linked into one shared library."""
 import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgbs.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("GBS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC",
     f"--offload-arch={ARCH}",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -25,13 +30,27 @@ def sources():
 
 def build(verbose: bool = False, extra=None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    jobs = []
+    for src in sources():
+        obj = os.path.join(OBJ_DIR, os.path.basename(src)[:-4] + ".o")
+        jobs.append((obj, [hipcc] + HIPCC_FLAGS + list(extra or []) + inc + ["-c", src, "-o", obj]))
+
+    def run(job):
+        if verbose:
+            print(" ".join(job[1]), flush=True)
+        subprocess.run(job[1], check=True)
+        return job[0]
+
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1)), 16))
+    with ThreadPoolExecutor(workers) as pool:
+        objs = list(pool.map(run, jobs))
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + list(extra or []) + [
-        "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-        "-o", tmp] + sources()
+    link = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(tmp, LIB)
     return LIB
 
