@@ -62,7 +62,9 @@ enum {
     GBS_E_NOT_SPD = 2,       /* a pivot of some Q_T was not positive and finite        */
     GBS_E_OUT_OF_MEMORY = 3, /* scratch allocation failed                              */
     GBS_E_DEVICE = 4,        /* a HIP runtime call failed                              */
-    GBS_E_UNSUPPORTED = 5    /* valid request that this library does not implement     */
+    GBS_E_UNSUPPORTED = 5,   /* valid request that this library does not implement     */
+    GBS_E_SCRATCH_LIMIT = 6  /* gbs_cumulants_noalloc: the problem needs more scratch than
+                                GBS_NOALLOC_SCRATCH_BYTES                               */
 };
 
 /* flags (bit set) */
@@ -139,6 +141,38 @@ GBS_API gbs_status gbs_correlators(int32_t M, const double* sigma, int32_t max_o
  * Other arguments as gbs_correlators. */
 GBS_API gbs_status gbs_cumulants(int32_t M, const double* sigma, int32_t max_order, int32_t flags,
                          double* corr, double* cum, void* stream);
+
+/* Static scratch of gbs_cumulants_noalloc, bytes per device (160 MiB). */
+#define GBS_NOALLOC_SCRATCH_BYTES (160u * 1024u * 1024u)
+
+/* gbs_cumulants for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, outputs, kernels and results as gbs_cumulants (bit for bit),
+ * but every scratch buffer of the call -- Q, its diagonal blocks, the
+ * mixed-precision operands, the status word, the group kernel's tile plans and
+ * the lower-order probability tables (and the correlator tables when corr is
+ * NULL) -- lives in one static device array of GBS_NOALLOC_SCRATCH_BYTES per
+ * device, held from the library's load until the process ends.  The call
+ * makes no hipMalloc, hipFree, stream-ordered or pinned-host allocation.
+ *   Limit: about 8 (N(M, K-1) [+ N(M, K) if corr is NULL] + 4 M^2) bytes plus
+ *   the tile plans (~3.5 MB at M = 144, K = 5) must fit: M = 144, K = 5 fits
+ *   with corr given, not with corr NULL.  Larger problems return
+ *   GBS_E_SCRATCH_LIMIT before anything is launched.
+ *   flags  GBS_CLICK/GBS_PARITY | GBS_MIXED | GBS_ASYNC | GBS_ALL_MINORS
+ *          (GBS_TIMING gives GBS_E_UNSUPPORTED: its events are allocations)
+ * Set-up: the first call on a device looks up the array's address there and
+ * writes a constant binomial table into it (a blocking copy); it must not be
+ * captured.  Tile plans are copied in (from host memory, on `stream`) when the
+ * previous call on the device had a different (M, max_order).
+ * Every call on one device shares that device's array and leaves its contents
+ * there: calls that overlap on one device (other threads, other streams, or a
+ * second call before the first has completed its kernels on another stream)
+ * race and give wrong results; serialise them.  The status word stays on the
+ * device: a synchronous call reads it back with a blocking copy, a
+ * GBS_ASYNC call leaves it for gbs_last_error (valid once the stream has
+ * completed).  Other errors as gbs_cumulants. */
+GBS_API gbs_status gbs_cumulants_noalloc(int32_t M, const double* sigma, int32_t max_order,
+                                         int32_t flags, double* corr, double* cum, void* stream);
 
 /* Correlators and cumulants of a DISPLACED Gaussian state (first moments
  * mu != 0).  The vacuum probability becomes

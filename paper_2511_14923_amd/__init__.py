@@ -11,7 +11,8 @@ from ._binding import (  # noqa: F401
     GBS_OK, GBS_PARITY, GBS_TIMING, GBSError, STAGE_NAMES, gbs_last_timings, LIB_PATH, gbs_autotune_batched, gbs_colex_rank,
     gbs_colex_unrank, gbs_correlators, gbs_cumulant_grad, gbs_cumulants, gbs_cumulants_batched,
     gbs_cumulants_displaced, gbs_sample, GBS_STAGE_SAMPLE, gbs_sample_cumulants, gbs_pearson,
-    GBS_STAGE_ESTIMATE, gbs_cumulants_shard,
+    GBS_STAGE_ESTIMATE, gbs_cumulants_shard, gbs_cumulants_noalloc, GBS_E_SCRATCH_LIMIT,
+    GBS_NOALLOC_SCRATCH_BYTES,
     gbs_last_error, gbs_num_subsets, gbs_order_offset, gbs_set_tuning, gbs_status_string,
     gbs_total_outputs, lib,
 )

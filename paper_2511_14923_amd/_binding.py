@@ -19,6 +19,8 @@ GBS_E_NOT_SPD = 2
 GBS_E_OUT_OF_MEMORY = 3
 GBS_E_DEVICE = 4
 GBS_E_UNSUPPORTED = 5
+GBS_E_SCRATCH_LIMIT = 6
+GBS_NOALLOC_SCRATCH_BYTES = 160 * 1024 * 1024
 
 GBS_CLICK = 0
 GBS_PARITY = 1
@@ -49,7 +51,7 @@ EXPORTS = (
     "gbs_cumulant_grad",
     "gbs_cumulants_batched", "gbs_autotune_batched", "gbs_set_tuning", "gbs_sample",
     "gbs_sample_cumulants", "gbs_pearson", "gbs_last_error",
-    "gbs_last_timings", "gbs_status_string",
+    "gbs_last_timings", "gbs_status_string", "gbs_cumulants_noalloc",
 )
 
 
@@ -103,6 +105,8 @@ def lib() -> ctypes.CDLL:
     L.gbs_correlators.restype = i32
     L.gbs_cumulants.argtypes = [i32, vp, i32, i32, vp, vp, vp]
     L.gbs_cumulants.restype = i32
+    L.gbs_cumulants_noalloc.argtypes = [i32, vp, i32, i32, vp, vp, vp]
+    L.gbs_cumulants_noalloc.restype = i32
     L.gbs_cumulants_displaced.argtypes = [i32, vp, vp, i32, i32, vp, vp, vp]
     L.gbs_cumulants_displaced.restype = i32
     L.gbs_cumulants_shard.argtypes = [i32, vp, i32, i64, i64, i32, vp, vp, vp]
@@ -289,6 +293,22 @@ def gbs_cumulants(M: int, sigma: torch.Tensor, max_order: int, flags: int = 0, c
         st = lib().gbs_cumulants(M, _ptr(sigma), max_order, flags, _ptr(corr), _ptr(cum),
                                  _stream(stream, sigma.device))
     _check(st, "gbs_cumulants")
+    return corr, cum
+
+
+def gbs_cumulants_noalloc(M: int, sigma: torch.Tensor, max_order: int, flags: int, corr, cum,
+                          stream=None) -> tuple:
+    """gbs_cumulants through the allocation-free entry point: the caller passes
+    every output buffer (corr may be None), nothing is allocated here either."""
+    n = _outputs(M, max_order)
+    _sigma(M, sigma)
+    _need(corr, "corr", n, optional=True)
+    _need(cum, "cum", n)
+    _same_device(("sigma", sigma), ("corr", corr), ("cum", cum))
+    with torch.cuda.device(sigma.device):
+        st = lib().gbs_cumulants_noalloc(M, _ptr(sigma), max_order, flags, _ptr(corr), _ptr(cum),
+                                         _stream(stream, sigma.device))
+    _check(st, "gbs_cumulants_noalloc")
     return corr, cum
 
 

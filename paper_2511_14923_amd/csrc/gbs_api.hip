@@ -28,6 +28,9 @@ struct ThreadError {
   int64_t rank = -1;
   bool pending_async = false;
   DeviceStatus* host_status = nullptr;  // pinned, written by the last async call
+  // status word of the last asynchronous allocation-free call, read back by
+  // gbs_last_error (null for the other entry points)
+  const DeviceStatus* pending_dev = nullptr;
 };
 thread_local ThreadError t_err;
 
@@ -166,6 +169,7 @@ ForwardScratch layout_scratch(char* base, int M, bool mixed, bool displaced) {
 
 // Queue the copy of the device status word to this thread's pinned slot.
 static gbs_status status_enqueue(DeviceStatus* dev_status, hipStream_t s) {
+  t_err.pending_dev = nullptr;
   if (!t_err.host_status) {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&t_err.host_status), sizeof(DeviceStatus),
                                  hipHostMallocDefault);
@@ -203,6 +207,33 @@ gbs_status finish_status(DeviceStatus* dev_status, int32_t flags, hipStream_t s)
   gbs_status st = status_enqueue(dev_status, s);
   if (st != GBS_OK) return st;
   return status_wait(flags, s);
+}
+
+// The end of a call that may not allocate: the status word stays on the
+// device; a synchronous call waits for the stream and reads it with a blocking
+// copy into host memory of its own, an asynchronous one leaves it for
+// gbs_last_error.
+gbs_status finish_status_device(const DeviceStatus* dev_status, int32_t flags, hipStream_t s) {
+  t_err.order = 0;
+  t_err.rank = -1;
+  if (flags & GBS_ASYNC) {
+    t_err.pending_async = true;
+    t_err.pending_dev = dev_status;
+    return GBS_OK;
+  }
+  t_err.pending_async = false;
+  t_err.pending_dev = nullptr;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return to_status(e);
+  DeviceStatus h{};
+  e = hipMemcpy(&h, dev_status, sizeof(h), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return to_status(e);
+  if (h.flag) {
+    t_err.order = h.order;
+    t_err.rank = h.rank;
+    return GBS_E_NOT_SPD;
+  }
+  return GBS_OK;
 }
 
 // Report the status, then release the call's stream-ordered scratch (the free
@@ -524,7 +555,14 @@ gbs_status gbs_pearson(int64_t n, const double* x, const double* y, double* r, i
 }
 
 gbs_status gbs_last_error(int32_t* order, int64_t* rank) {
-  if (t_err.pending_async && t_err.host_status) {
+  if (t_err.pending_async && t_err.pending_dev) {
+    // an allocation-free call: its status word is still on the device
+    DeviceStatus h{};
+    if (hipMemcpy(&h, t_err.pending_dev, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+      return GBS_E_DEVICE;
+    t_err.order = h.flag ? h.order : 0;
+    t_err.rank = h.flag ? h.rank : -1;
+  } else if (t_err.pending_async && t_err.host_status) {
     // valid once the stream of the last asynchronous call has completed
     if (t_err.host_status->flag) {
       t_err.order = t_err.host_status->order;
@@ -563,6 +601,9 @@ const char* gbs_status_string(gbs_status s) {
     case GBS_E_OUT_OF_MEMORY: return "out of device memory";
     case GBS_E_DEVICE: return "HIP runtime error";
     case GBS_E_UNSUPPORTED: return "unsupported request";
+    case GBS_E_SCRATCH_LIMIT:
+      return "the problem needs more than the allocation-free entry point's static scratch "
+             "(GBS_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown status";
   }
 }

@@ -350,6 +350,9 @@ hipError_t get_plan(int M, int NB, int kB, Plan* out) {
   return hipSuccess;
 }
 
+std::mutex g_host_plan_mu;
+std::map<PlanKey, std::vector<uint64_t>> g_host_plans;
+
 template <int NB, bool DISP>
 int group_windows(int M) {
   return (GroupLayout<NB, DISP>::kB * (M - NB) + 63) / 64 + 1;
@@ -385,15 +388,36 @@ bool group_supported(int d, int M, int flags, bool displaced) {
   return lds <= 64 * 1024;
 }
 
+const std::vector<uint64_t>& group_plan_host(int d, int M) {
+  const int NB = d - 1;
+  const int kB = GroupLayout<2, false>::kB;  // the zero-mean tile width (same for every order)
+  std::lock_guard<std::mutex> lock(g_host_plan_mu);
+  auto it = g_host_plans.find(PlanKey{-1, M, NB, kB});
+  if (it == g_host_plans.end())
+    it = g_host_plans.emplace(PlanKey{-1, M, NB, kB}, plan_tiles(M, NB, group_rmax(M, NB), kB)).first;
+  return it->second;  // map nodes are never erased: the reference stays valid
+}
+
+uint32_t group_plan_grid(uint32_t ntiles, int cu_count) {
+  return std::min<uint32_t>(ntiles, (uint32_t)std::max(cu_count, 1) * kGroupWgPerCU);
+}
+
 template <int D, int CONV, bool WC, bool DISP>
 static hipError_t launch_group_t(int M, const double* Qi, const double* Qd, const double* mi,
                                  const uint64_t* binom, const OrderTables& tab, double* m_out,
-                                 double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
+                                 double* k_out, double* p_out, DeviceStatus* st, hipStream_t s,
+                                 const GroupPlanRef* ext) {
   constexpr int NB = D - 1;
   if (host_binom(M, D) == 0) return hipSuccess;
   Plan plan;
-  hipError_t e = get_plan(M, NB, GroupLayout<NB, DISP>::kB, &plan);
-  if (e != hipSuccess) return e;
+  if (ext) {
+    plan.dev = const_cast<uint64_t*>(ext->dev);
+    plan.ntiles = ext->ntiles;
+    plan.grid = ext->grid;
+  } else {
+    hipError_t e = get_plan(M, NB, GroupLayout<NB, DISP>::kB, &plan);
+    if (e != hipSuccess) return e;
+  }
   if (plan.ntiles == 0) return hipSuccess;
   const int nwin = group_windows<NB, DISP>(M);
   const size_t lds = group_lds<NB, DISP>(M);
@@ -406,30 +430,32 @@ static hipError_t launch_group_t(int M, const double* Qi, const double* Qd, cons
 template <int D, int CONV, bool DISP>
 static hipError_t launch_group_w(int M, const double* Qi, const double* Qd, const double* mi,
                                  const uint64_t* binom, const OrderTables& tab, double* m_out,
-                                 double* k_out, double* p_out, DeviceStatus* st, hipStream_t s) {
+                                 double* k_out, double* p_out, DeviceStatus* st, hipStream_t s,
+                                 const GroupPlanRef* ext) {
   if (k_out)
     return launch_group_t<D, CONV, true, DISP>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st,
-                                               s);
+                                               s, ext);
   return launch_group_t<D, CONV, false, DISP>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st,
-                                              s);
+                                              s, ext);
 }
 
 template <int D>
 static hipError_t launch_group_c(int M, int flags, const double* Qi, const double* Qd,
                                  const double* mi, const uint64_t* binom, const OrderTables& tab,
                                  double* m_out, double* k_out, double* p_out, DeviceStatus* st,
-                                 hipStream_t s) {
+                                 hipStream_t s, const GroupPlanRef* ext) {
   if (flags & GBS_PARITY) {
     if (mi)
       return launch_group_w<D, GBS_PARITY, true>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out,
-                                                 st, s);
+                                                 st, s, nullptr);
     return launch_group_w<D, GBS_PARITY, false>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out,
-                                                st, s);
+                                                st, s, ext);
   }
   if (mi)
     return launch_group_w<D, GBS_CLICK, true>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st,
-                                              s);
-  return launch_group_w<D, GBS_CLICK, false>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s);
+                                              s, nullptr);
+  return launch_group_w<D, GBS_CLICK, false>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s,
+                                             ext);
 }
 
 void group_tiles(int d, int M, std::vector<uint64_t>* out) {
@@ -513,11 +539,11 @@ hipError_t launch_group_batched(int d, int flags, const GroupBatchInstance* inst
 hipError_t launch_forward_group(int d, int M, int flags, const double* Qi, const double* Qd,
                                 const double* mi, const uint64_t* binom, const OrderTables& tab,
                                 double* m_out, double* k_out, double* p_out, DeviceStatus* st,
-                                hipStream_t s) {
+                                hipStream_t s, const GroupPlanRef* plan) {
   switch (d) {
-    case 3: return launch_group_c<3>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s);
-    case 4: return launch_group_c<4>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s);
-    case 5: return launch_group_c<5>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s);
+    case 3: return launch_group_c<3>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s, plan);
+    case 4: return launch_group_c<4>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s, plan);
+    case 5: return launch_group_c<5>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s, plan);
     default: return hipErrorInvalidValue;
   }
 }

@@ -496,7 +496,7 @@ hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const d
                               const float* E, const uint64_t* binom, const double* const* p_tab,
                               const double* const* m_tab, const double* const* k_tab,
                               double* m_out, double* k_out, double* p_out, DeviceStatus* st,
-                              hipStream_t s) {
+                              hipStream_t s, const GroupPlanRef* plans) {
   if (mi && (flags & GBS_MIXED)) return hipErrorInvalidValue;
   OrderTables tab{};
   for (int q = 1; q <= kMaxOrder; ++q) {
@@ -526,7 +526,8 @@ hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const d
   }
   // the tile kernel takes zero-mean states only
   if (group_supported(d, M, flags, mi != nullptr))
-    return launch_forward_group(d, M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s);
+    return launch_forward_group(d, M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s,
+                                (plans && !mi) ? &plans[d] : nullptr);
   if (!mi && tile_supported(d, M, flags))
     return launch_forward_tile(d, M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
   switch (d) {

@@ -51,6 +51,12 @@ hipError_t timing_end(hipStream_t s);
 // status word back; synchronise and report unless GBS_ASYNC).
 gbs_status to_status(hipError_t e);
 gbs_status finish_status(DeviceStatus* dev_status, int32_t flags, hipStream_t s);
+// The same without the pinned host slot (the allocation-free entry point): the
+// status word is read back by a blocking copy, or by gbs_last_error after an
+// asynchronous call.
+gbs_status finish_status_device(const DeviceStatus* dev_status, int32_t flags, hipStream_t s);
+// Argument check shared by the forward entry points (M, max_order, flag bits).
+bool valid_problem(int32_t M, int32_t K, int32_t flags);
 
 // Reset a status word (fill kernel, safe inside graph capture).
 hipError_t launch_clear_status(DeviceStatus* st, hipStream_t s);
@@ -97,10 +103,23 @@ hipError_t launch_forward_tile(int d, int M, int flags, const double* Qi, const 
 // tile width) and kept on the device until the process ends.  mi: interleaved
 // first moments of a displaced state, or null.
 bool group_supported(int d, int M, int flags, bool displaced);
+// A tile plan already on the device (caller-placed): ntiles descriptors at dev,
+// launched on `grid` workgroups.  Passed to launch_forward_group to bypass the
+// library's own cached plans (which it allocates once per (M, d)).
+struct GroupPlanRef {
+  const uint64_t* dev = nullptr;
+  uint32_t ntiles = 0;
+  uint32_t grid = 0;
+};
+// Host copy of the zero-mean tile plan of order d for M modes (built once,
+// kept until the process ends) and the grid a single-instance launch uses
+// on a device with cu_count compute units.
+const std::vector<uint64_t>& group_plan_host(int d, int M);
+uint32_t group_plan_grid(uint32_t ntiles, int cu_count);
 hipError_t launch_forward_group(int d, int M, int flags, const double* Qi, const double* Qd,
                                 const double* mi, const uint64_t* binom, const OrderTables& tab,
                                 double* m_out, double* k_out, double* p_out, DeviceStatus* st,
-                                hipStream_t s);
+                                hipStream_t s, const GroupPlanRef* plan = nullptr);
 
 // The group kernel over many zero-mean instances: one persistent launch per
 // order claims (instance, tile) items from a device work list.  Instance i of
@@ -137,12 +156,14 @@ hipError_t launch_group_batched(int d, int flags, const GroupBatchInstance* inst
 // (q < d); m_out, k_out, p_out at the order-d blocks (each may be null).
 // GBS_MIXED reads pk and E (normalised Q) instead of Qi.  mi (interleaved first
 // moments, FP64 only) selects the displaced-state kernels; null for zero mean.
+// plans (may be null): plans[d] is the device tile plan the group kernel of
+// order d uses instead of the library's cached one (zero-mean states only).
 hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const double* Qd,
                               const double* mi, const double* pk,
                               const float* E, const uint64_t* binom, const double* const* p_tab,
                               const double* const* m_tab, const double* const* k_tab,
                               double* m_out, double* k_out, double* p_out, DeviceStatus* st,
-                              hipStream_t s);
+                              hipStream_t s, const GroupPlanRef* plans = nullptr);
 
 // Vector-Jacobian product given the forward correlators m and vacuum
 // probabilities ptab of every subset (orders 1..K); d1, mbar, pbar are scratch
