@@ -102,18 +102,25 @@ typedef struct {
 #define GBS_MAX_ORDER 5
 #define GBS_MAX_MODES 2048
 
-/* host.  C(M, d) for 0 <= d <= M <= GBS_MAX_MODES; -1 otherwise. */
+/* host.  C(M, d) for 0 <= d <= M <= GBS_MAX_MODES; -1 otherwise.  The number of
+ * order-d correlators (the subsets S with |S| = d of Sec. I.A, counted in the
+ * space estimate of Sec. "Cost estimation and scaling"). */
 GBS_API int64_t gbs_num_subsets(int32_t M, int32_t d);
 
 /* host.  Start of the order-d block: sum_{e=1..d-1} C(M, e); -1 on bad arguments
- * (1 <= d <= GBS_MAX_ORDER + 1, d <= M + 1). */
+ * (1 <= d <= GBS_MAX_ORDER + 1, d <= M + 1).  Output layout of this library
+ * (the paper keeps explicit subset lists with auxiliary indices, Sec. III
+ * Phase I; here order blocks and colex ranks replace them). */
 GBS_API int64_t gbs_order_offset(int32_t M, int32_t d);
 
-/* host.  N(M, K) = total number of outputs for orders 1..K; -1 on bad arguments. */
+/* host.  N(M, K) = total number of outputs for orders 1..K; -1 on bad arguments
+ * (all subsets up to the truncation order K of Sec. I.A). */
 GBS_API int64_t gbs_total_outputs(int32_t M, int32_t max_order);
 
 /* host.  Colex rank of the d-subset S (host array of d distinct modes in any
- * order, each in [0, GBS_MAX_MODES)); -1 on bad arguments. */
+ * order, each in [0, GBS_MAX_MODES)); -1 on bad arguments.  The position of S
+ * inside its order block (combinatorial number system; replaces the subset
+ * lists of Sec. III Phase I). */
 GBS_API int64_t gbs_colex_rank(int32_t d, const int32_t* S);
 
 /* host.  Inverse of gbs_colex_rank: writes the d-subset of rank r, ascending,
@@ -121,7 +128,10 @@ GBS_API int64_t gbs_colex_rank(int32_t d, const int32_t* S);
  * [1, GBS_MAX_ORDER], r < 0, or the subset would need a mode >= GBS_MAX_MODES. */
 GBS_API gbs_status gbs_colex_unrank(int32_t d, int64_t r, int32_t* S);
 
-/* Correlators only (the cumulant stage is skipped).
+/* Correlators only (the cumulant stage is skipped): mu(S) by inclusion-exclusion
+ * over the vacuum probabilities of the subsets of S (App. A.2, Eq.
+ * joint_moments_def; App. D.1, Eq. correlator_sum_cov), or the parity
+ * correlator c(S) (Sec. I.A, Eq. corre_cov_main).
  *   M          number of modes, 1 <= M <= GBS_MAX_MODES
  *   sigma      device, 2M x 2M FP64 (layout above)
  *   max_order  K, 1 <= K <= min(GBS_MAX_ORDER, M)
@@ -213,7 +223,12 @@ GBS_API gbs_status gbs_cumulants_shard(int32_t M, const double* sigma, int32_t o
                                        void* stream);
 
 /* Vector-Jacobian product of gbs_cumulants (FP64 only; GBS_MIXED gives
- * GBS_E_UNSUPPORTED):
+ * GBS_E_UNSUPPORTED).  Not in the paper (it has no gradients): derived from
+ * App. D.1, Eq. correlator_sum_cov, with d log det A = tr(A^{-1} dA).  The
+ * fifth argument is the upstream gradient of the correlators, not the forward
+ * correlators: the forward pass (vacuum probabilities and correlators of every
+ * subset) is recomputed inside the call, so one call serves losses on the
+ * correlators, the cumulants or both:
  *   grad_sigma[i][j] = sum_S grad_corr[S] d corr[S]/d sigma_ij
  *                    + sum_S grad_cum[S]  d cum[S] /d sigma_ij
  * with the 4M^2 entries of sigma treated as independent variables, so the
@@ -236,7 +251,10 @@ typedef struct {
     double* cum;         /* device, N(M, K) FP64 (required)                                   */
 } gbs_instance;
 
-/* Many instances of uneven M in persistent launches over device work lists
+/* gbs_cumulants for many covariance instances at once (the same definitions:
+ * Sec. I.A, Eqs. corre_cov_main and cumulant_corr_main; App. A.2; the batching
+ * itself is not in the paper, which computes one ground truth per run).
+ * Many instances of uneven M in persistent launches over device work lists
  * (plus the launches that form every instance's Q): one launch over
  * (instance, order, rank range) items evaluated from all the principal minors
  * of Q_S (orders 1 and 2; every order with GBS_MIXED or GBS_ALL_MINORS, and
@@ -247,8 +265,11 @@ typedef struct {
  * per instance list: Q and its diagonal blocks, and, for the group launches,
  * the vacuum probabilities of orders 1..max_order-1 (and their correlators when
  * inst.corr is NULL).  The pipeline is captured once into a HIP graph per
- * (instance list, order, flags, tuning) and replayed on later calls with the
- * same list; the all-minors launch takes its block shape and unroll from
+ * (instance list, stream, order, flags, tuning) and replayed on later calls
+ * with the same list on the same stream (a plan's work-list counter and status
+ * word serve one stream: threads calling on one stream are serialised while
+ * they enqueue, a list used on two streams gets two plans, and an evicted plan
+ * is freed only after its last call has returned); the all-minors launch takes its block shape and unroll from
  * gbs_autotune_batched's cached choice when one exists for this device, else
  * from a fixed default; the group launches fill the device.
  *   n      1 <= n <= 4096
@@ -265,13 +286,15 @@ typedef struct {
     int32_t waves_per_cu; /* persistent workgroups per compute unit, 1..8   */
 } gbs_tuning;
 
-/* Times every candidate shape on the given batch (outputs are overwritten,
+/* Launch-shape autotuner of gbs_cumulants_batched (library plumbing, not in the
+ * paper).  Times every candidate shape on the given batch (outputs are overwritten,
  * stream-ordered, synchronising) and caches the fastest for this device,
  * order and precision; writes it to *best (host) when best is non-NULL. */
 GBS_API gbs_status gbs_autotune_batched(int32_t n, const gbs_instance* inst, int32_t max_order,
                                 int32_t flags, void* stream, gbs_tuning* best);
 
-/* host.  Set (or, with t == NULL, clear) the cached shape used by
+/* host (library plumbing, not in the paper).  Set (or, with t == NULL, clear)
+ * the cached shape used by
  * gbs_cumulants_batched for this device, order and precision. */
 GBS_API gbs_status gbs_set_tuning(int32_t max_order, int32_t flags, const gbs_tuning* t);
 
@@ -335,17 +358,20 @@ GBS_API gbs_status gbs_sample_cumulants(int32_t M, int64_t nsamples, const uint8
 GBS_API gbs_status gbs_pearson(int64_t n, const double* x, const double* y, double* r,
                                int32_t flags, void* stream);
 
-/* host.  After a call returned GBS_E_NOT_SPD (or after a GBS_ASYNC call's
+/* host (error reporting, not in the paper: a Q_T that is not positive definite
+ * has no vacuum probability, App. D.1).  After a call returned GBS_E_NOT_SPD
+ * (or after a GBS_ASYNC call's
  * stream completed), the order and colex rank of the first failing subset
  * seen by this thread's last call; GBS_OK if none.  Either pointer may be NULL. */
 GBS_API gbs_status gbs_last_error(int32_t* order, int64_t* rank);
 
-/* host.  Kernel timings of this thread's last call made with GBS_TIMING: waits
+/* host (measurement plumbing, not in the paper).  Kernel timings of this
+ * thread's last call made with GBS_TIMING: waits
  * for its events, writes up to `capacity` entries (launch order) to `out` and
  * returns the number of entries recorded (-1 on a HIP error). */
 GBS_API int32_t gbs_last_timings(int32_t capacity, gbs_kernel_time* out);
 
-/* host.  Static description of a status code. */
+/* host (library plumbing, not in the paper).  Static description of a status code. */
 GBS_API const char* gbs_status_string(gbs_status s);
 
 #ifdef __cplusplus

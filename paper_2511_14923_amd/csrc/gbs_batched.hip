@@ -25,6 +25,7 @@
 #include <cstring>
 #include <list>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -265,6 +266,16 @@ struct BatchPlan {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // the caller's stream: a plan serves one stream, whose order serialises the
+  // calls that share its counter and status word
+  hipStream_t stream = nullptr;
+  // held while a call enqueues this plan's launches (threads sharing a stream)
+  std::mutex launch_mu;
+
+  ~BatchPlan() {
+    if (mem) (void)hipDeviceSynchronize();  // the last holder frees it; its work may be queued
+    release();
+  }
 
   void release() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -279,12 +290,16 @@ struct BatchPlan {
 };
 
 std::mutex g_plan_mutex;
-std::list<BatchPlan*> g_plans;  // most recent first
+// most recent first; shared so that an evicted plan lives until the calls
+// that hold it return
+std::list<std::shared_ptr<BatchPlan>> g_plans;
 constexpr size_t kMaxPlans = 8;
 
-bool same_key(const BatchPlan* p, int dev, int n, const gbs_instance* inst, int K, int flags,
-              const gbs_tuning& t) {
-  if (p->device != dev || p->K != K || p->flags != flags || (int)p->key.size() != n) return false;
+bool same_key(const BatchPlan* p, int dev, hipStream_t s, int n, const gbs_instance* inst, int K,
+              int flags, const gbs_tuning& t) {
+  if (p->device != dev || p->stream != s || p->K != K || p->flags != flags ||
+      (int)p->key.size() != n)
+    return false;
   if (p->tuning.block != t.block || p->tuning.unroll != t.unroll || p->tuning.tile != t.tile ||
       p->tuning.waves_per_cu != t.waves_per_cu)
     return false;
@@ -541,11 +556,11 @@ gbs_status run_batched(int n, const gbs_instance* inst, int K, int flags, void* 
   if (!ctx) return to_status(e);
   const int key_flags = flags & (GBS_PARITY | GBS_MIXED | GBS_ALL_MINORS);
   const gbs_tuning t = lookup_tuning(ctx->device, K, flags);
-  BatchPlan* plan = nullptr;
+  std::shared_ptr<BatchPlan> plan;
   {
     std::lock_guard<std::mutex> lock(g_plan_mutex);
     for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
-      if (same_key(*it, ctx->device, n, inst, K, key_flags, t)) {
+      if (same_key(it->get(), ctx->device, s, n, inst, K, key_flags, t)) {
         plan = *it;
         g_plans.erase(it);
         g_plans.push_front(plan);
@@ -554,24 +569,16 @@ gbs_status run_batched(int n, const gbs_instance* inst, int K, int flags, void* 
     }
   }
   if (!plan) {
-    plan = new BatchPlan();
-    gbs_status st = build_plan(plan, n, inst, K, key_flags, t);
-    if (st == GBS_OK) st = capture_plan(plan);
-    if (st != GBS_OK) {
-      plan->release();
-      delete plan;
-      return st;
-    }
+    plan = std::make_shared<BatchPlan>();
+    plan->stream = s;
+    gbs_status st = build_plan(plan.get(), n, inst, K, key_flags, t);
+    if (st == GBS_OK) st = capture_plan(plan.get());
+    if (st != GBS_OK) return st;  // the destructor releases what was built
     std::lock_guard<std::mutex> lock(g_plan_mutex);
     g_plans.push_front(plan);
-    while (g_plans.size() > kMaxPlans) {
-      BatchPlan* old = g_plans.back();
-      g_plans.pop_back();
-      (void)hipDeviceSynchronize();
-      old->release();
-      delete old;
-    }
+    while (g_plans.size() > kMaxPlans) g_plans.pop_back();  // freed by its last holder
   }
+  std::lock_guard<std::mutex> launch(plan->launch_mu);
   if (flags & GBS_TIMING) {
     // same kernels, launched one by one so that each gets its event pair
     timing_start_call(true);
