@@ -39,12 +39,14 @@ __device__ __forceinline__ void latch_failure(DeviceStatus* st, int order, int64
 // 1/sqrt(x) in FP64: hardware estimate refined by two Newton steps
 // y <- y + y (1 - x y^2) / 2, each step squaring the relative error.
 __device__ __forceinline__ double rsqrt_f64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double e = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  e = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  return y;
+  // The instruction's estimate y is good to about 2^-25 relative; one step of
+  // Halley's iteration for x y^2 = 1, y <- y (1 + e/2 + 3e^2/8) with
+  // e = 1 - x y^2, leaves an error of order e^3 below the final rounding
+  // (measured within 1 ulp, like two Newton steps, at five operations
+  // instead of eight).
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
 // Packed lower triangle of an N x N symmetric matrix.

@@ -59,6 +59,17 @@ constexpr int kGroupRmax = 148;     // (T, a) records per tile at most (M - d + 
 // every grid-th tile (order 5 at M = 144: 7.31 -> 6.83 ms against one workgroup
 // per tile, ~430,000 tiles).
 constexpr uint32_t kGroupWgPerCU = 192;
+// Tile descriptor (64 bits): the colex rank of the tile's first B (29 bits),
+// the number of B's (6 bits), and the modes of that B's T (8 bits each), so
+// that each lane finds its B by walking the groups from the first one instead
+// of unranking.  The group kernel runs only where every rank fits in 29 bits
+// and M <= 152 (group_supported).
+constexpr int kDescNbShift = 29;
+constexpr int kDescTShift = 35;
+constexpr uint64_t kDescBetaMask = (1ull << kDescNbShift) - 1;
+// steps of a lane's walk at most: the groups of a tile (kGroupG) and the empty
+// T (min T = 0) between them, at most two per group
+constexpr int kWalkMax = 3 * kGroupG + 4;
 
 template <int NB, bool DISP>
 struct GroupLayout {
@@ -128,6 +139,22 @@ __host__ __device__ constexpr int gop_index(int u) {
   return n;
 }
 
+// Colex successor of the NT-subset t of [0, M) (unchanged for the last one).
+template <int NT>
+__device__ __forceinline__ void colex_next(int (&t)[NT], int M) {
+  bool done = false;
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const int lim = (i + 1 < NT) ? t[i + 1] : M;
+    if (!done && t[i] + 1 < lim) {
+      ++t[i];
+#pragma unroll
+      for (int j = 0; j < i; ++j) t[j] = j;
+      done = true;
+    }
+  }
+}
+
 // Leading sets of T in the order [P, e]: empty, {P_0}, .., P, T.
 template <int NT>
 __host__ __device__ constexpr bool t_leading(int t) {
@@ -138,7 +165,7 @@ __host__ __device__ constexpr bool t_leading(int t) {
 
 // One instance: one workgroup per tile of the plan.
 template <int D, int CONV, bool WANT_CUM, bool DISP>
-__global__ __launch_bounds__(kGroupThreads) void forward_group_kernel(
+__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(1, 3))) void forward_group_kernel(
     const double* __restrict__ Qi, const double* __restrict__ Qd,
     const double* __restrict__ mi, int M,
     const uint64_t* __restrict__ plan, uint32_t ntiles, const uint64_t* __restrict__ binom,
@@ -262,10 +289,12 @@ namespace {
 std::vector<uint64_t> plan_tiles(int M, int NB, int rmax, int kB) {
   std::vector<uint64_t> tiles;
   uint32_t beta = 0, tstart = 0;
+  uint64_t tfirst = 0;  // modes of the T of the tile's first B, 8 bits each
   int nB = 0, rec = 0, ng = 0;
   auto close = [&]() {
-    if (nB > 0) tiles.push_back((uint64_t)tstart | ((uint64_t)nB << 32));
-    tstart = beta;
+    if (nB > 0)
+      tiles.push_back((uint64_t)tstart | ((uint64_t)nB << kDescNbShift) |
+                      (tfirst << kDescTShift));
     nB = 0;
     rec = 0;
     ng = 0;
@@ -284,6 +313,11 @@ std::vector<uint64_t> plan_tiles(int M, int NB, int rmax, int kB) {
         close();
         n = std::min(gsize - k, kB);
         need = k + n - 1;
+      }
+      if (nB == 0) {  // the tile starts at B = {k} + T, colex rank beta
+        tstart = beta;
+        tfirst = 0;
+        for (int j = 0; j < nt; ++j) tfirst |= (uint64_t)t[j] << (8 * j);
       }
       nB += n;
       rec += need;
@@ -383,7 +417,7 @@ bool group_supported(int d, int M, int flags, bool displaced) {
   if (d < 3 || d > kMaxOrder || (flags & GBS_MIXED)) return false;
   for (int q = 1; q <= d; ++q)
     if (host_binom(M, q) >= (1ull << 29)) return false;
-  if (group_rmax(M, d - 1) < 0) return false;
+  if (group_rmax(M, d - 1) < 0 || M > 255) return false;
   const size_t lds = displaced ? group_lds_d<true>(d, M) : group_lds_d<false>(d, M);
   return lds <= 64 * 1024;
 }
