@@ -71,7 +71,7 @@ constexpr uint64_t kDescBetaMask = (1ull << kDescNbShift) - 1;
 // T (min T = 0) between them, at most two per group
 constexpr int kWalkMax = 3 * kGroupG + 4;
 
-template <int NB, bool DISP>
+template <int NB, bool DISP, bool MIXED = false>
 struct GroupLayout {
   // B's per tile: fewer for displaced states, whose larger records must still
   // let three workgroups share a compute unit's LDS
@@ -84,12 +84,17 @@ struct GroupLayout {
   static constexpr int NP = 1 << (NB - 1); // subsets of B' = B \ {e}
   static constexpr int FULL = NU - 1;
   static constexpr int FULLP = NP - 1;
-  // per-B record, doubles
+  // Factor entries (rows of Cholesky factors, forward substitutions, Schur
+  // complements) are FP64, or FP32 deviations from the identity of the
+  // normalised Q in the mixed form; probabilities, correlators and cumulants
+  // are FP64 in both.
+  // per-B record: the factor rows first (in factor-entry units), then doubles
   static constexpr int dLb = 0;                 // b_0 rows: [r][k < 2|P|], then 1/L, L, 1/L of the b_0 block
   static constexpr int nLb = 4 * NPm + 3;
   static constexpr int dLe = dLb + nLb;         // e rows against b_0 ([r][2]), then the e block
   static constexpr int nLe = 7;
-  static constexpr int dP = dLe + nLe;          // p(B'), p(B) (displaced: with exp(-|z|^2 / 2))
+  static constexpr int nL = nLb + nLe;
+  static constexpr int dP = MIXED ? (nL + 1) / 2 : nL;  // p(B'), p(B) (displaced: with exp(-|z|^2 / 2))
   static constexpr int dMB = dP + 2;            // m(B)
   static constexpr int dMW = dMB + 1;           // m(W), W = 1 .. FULLP (index W - 1)
   static constexpr int dKB = dMW + (NP - 1);    // k(R + e), R = 0 .. FULLP
@@ -99,7 +104,7 @@ struct GroupLayout {
   static constexpr int nDpad = (nD + 1) & ~1;
   // per-B record, 32-bit words
   static constexpr int wStart = 0;              // first rank of the B-block, tile relative
-  static constexpr int wRow = 1;                // byte offset of row 2 b_0 of Q
+  static constexpr int wRow = 1;                // byte offset of row 2 b_0 of Q (of E, mixed)
   static constexpr int wRbase = 2;              // (T, a) record of a = 0 for this B's group
   static constexpr int wOP = 3;                 // rank parts (less start) of p({a} + U), b_0 in U
   static constexpr int nOP = NP - 2;            // all U containing b_0 except B' and B
@@ -107,26 +112,32 @@ struct GroupLayout {
   static constexpr int nW = wG + (DISP ? 1 : 0);
   static constexpr int nWpad = (nW + 3) & ~3;
   static constexpr int bytes = nDpad * 8 + nWpad * 4;
-  // (T, a) record, doubles; stored as 16-byte units, unit q of record i at
-  // [q][i], so that consecutive records (consecutive a across a wavefront) fall
-  // in consecutive LDS banks
-  static constexpr int rY = 0;                  // y_P [k < 2|P|][2]
-  static constexpr int rT = rY + 4 * NPm;       // t_e [r][2]
-  static constexpr int rS = rT + 4;             // Schur complement of Q_P in Q_{P + a}: s00, s10, s11
-  static constexpr int rPT = rS + 4;            // p({a} + U), U subset of T (T bit i <-> B bit i + 1)
-  static constexpr int rN = rPT + NTS;
-  static constexpr int rUnits = (rN + 1) / 2;
+  // (T, a) record in 16-byte units, unit q of record i at [q][i], so that
+  // consecutive records (consecutive a across a wavefront) fall in consecutive
+  // LDS banks.  FP64: y_P row k is unit uY + k (two columns); mixed: unit
+  // uY + k/2 holds rows k, k + 1.
+  static constexpr int I0 = 2 * NPm;            // rows of P
+  static constexpr int uY = 0;                  // y_P [k < 2|P|][2]
+  static constexpr int uT = MIXED ? I0 / 2 : I0;        // t_e [r][2]
+  static constexpr int uS = uT + (MIXED ? 1 : 2);       // Schur complement of Q_P in Q_{P + a}: s00, s10, s11
+  static constexpr int uPK = uS + (MIXED ? 1 : 2);      // mixed: p_a = det(Q_aa)^(-1/2) (FP64)
+  static constexpr int uPT = uPK + (MIXED ? 1 : 0);     // nu, nue of the W subset of P (FP64)
+  static constexpr int rUnits = uPT + (NTS + 1) / 2;
   static constexpr int rbytes = rUnits * 16;    // per record
   // per-group record (Cholesky of Q_T in the order P, e), doubles
-  static constexpr int I0 = 2 * NPm;            // rows of P
   static constexpr int gP = 0;                  // L_P: tri(i, j), 1/L_ii on the diagonal
   static constexpr int gE = gP + tri_size(I0);  // e rows against P: [r][k < I0]
   static constexpr int gS = gE + 2 * I0;        // Q_ee - L_eP L_eP^T: s00, s10, s11
   static constexpr int gEd = gS + 3;            // e block of Q_T: 1/L, L, 1/L
-  static constexpr int gpP = gEd + 3;           // p(P) (displaced: with exp(-|z_P|^2 / 2))
-  static constexpr int gpT = gpP + 1;           // p(T) (displaced: with exp(-|z_T|^2 / 2))
+  static constexpr int gpP = gEd + 3;           // p(P) (displaced: with exp(-|z_P|^2 / 2); mixed: P_P)
+  static constexpr int gpT = gpP + 1;           // p(T) (displaced: with exp(-|z_T|^2 / 2); mixed: P_T)
   static constexpr int gZ = gpT + 1;            // displaced: z_P [2|P|], z_e(T) [2]
-  static constexpr int gN = ((gZ + (DISP ? I0 + 2 : 0)) + 1) & ~1;
+  // mixed: per block j of P, rho and P = prod p_k of the leading modes P_0..P_j,
+  // then rho_T (P_T is gpT)
+  static constexpr int gRho = gpT + 1;
+  static constexpr int gPP = gRho + NPm;
+  static constexpr int gRT = gPP + NPm;
+  static constexpr int gN = ((MIXED ? gRT + 1 : gZ + (DISP ? I0 + 2 : 0)) + 1) & ~1;
   static constexpr int gbytes = gN * 8;
 };
 
@@ -155,6 +166,22 @@ __device__ __forceinline__ void colex_next(int (&t)[NT], int M) {
   }
 }
 
+// Mixed form (FP32 deviations from the identity of the normalised Q):
+// det(I + S) - 1 of a 2x2 deviation S, without forming 1 + s_ii
+__device__ __forceinline__ float det_dev(float s00, float s10, float s11) {
+  return s00 + s11 + fmaf(s00, s11, -s10 * s10);
+}
+// (1 + delta)^(-1/2) - 1 = -delta y^2 / (1 + y), y = (1 + delta)^(-1/2)
+__device__ __forceinline__ float inv_sqrt_dev(float delta, float y) {
+  return -delta * y * y * __builtin_amdgcn_rcpf(1.0f + y);
+}
+// (1 + r)(1 + e) - 1
+__device__ __forceinline__ float dev_compose(float r, float e) { return r + fmaf(r, e, e); }
+// Two floats at a 32-bit byte offset (8-byte aligned) from a uniform base.
+__device__ __forceinline__ float2 load_f2_at(const float* __restrict__ base, uint32_t byte_off) {
+  return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 // Leading sets of T in the order [P, e]: empty, {P_0}, .., P, T.
 template <int NT>
 __host__ __device__ constexpr bool t_leading(int t) {
@@ -163,17 +190,20 @@ __host__ __device__ constexpr bool t_leading(int t) {
 
 }  // namespace
 
-// One instance: one workgroup per tile of the plan.
-template <int D, int CONV, bool WANT_CUM, bool DISP>
+// One instance: one workgroup per tile of the plan.  FP64 reads Q (and the
+// interleaved first moments mi of a displaced state); the mixed form reads the
+// single-mode vacuum probabilities pk and the FP32 normalised couplings E.
+template <int D, int CONV, bool WANT_CUM, bool DISP, bool MIXED>
 __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(1, 3))) void forward_group_kernel(
     const double* __restrict__ Qi, const double* __restrict__ Qd,
-    const double* __restrict__ mi, int M,
+    const double* __restrict__ mi, const double* __restrict__ pk, const float* __restrict__ E,
+    int M,
     const uint64_t* __restrict__ plan, uint32_t ntiles, const uint64_t* __restrict__ binom,
     OrderTables tab, double* __restrict__ m_out, double* __restrict__ k_out,
     double* __restrict__ p_out, DeviceStatus* __restrict__ st, int nwin_max) {
   constexpr int rmax = kGroupRmax;
   constexpr int NB = D - 1;
-  using GL = GroupLayout<NB, DISP>;
+  using GL = GroupLayout<NB, DISP, MIXED>;
   constexpr int NPm = GL::NPm;
   constexpr int NT = GL::NT;
   constexpr int NTS = GL::NTS;
@@ -203,7 +233,9 @@ __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(1
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const uint32_t ldq8 = 2u * (uint32_t)M * (uint32_t)sizeof(double);
-  const double* Qodd = Qi + 2 * (size_t)M;  // odd rows (p quadratures)
+  const double* Qodd = MIXED ? nullptr : Qi + 2 * (size_t)M;  // odd rows (p quadratures)
+  const uint32_t lde4 = 2u * (uint32_t)M * (uint32_t)sizeof(float);
+  const float* Eodd = MIXED ? E + 2 * (size_t)M : nullptr;
 
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t desc = plan[tile];
@@ -221,6 +253,7 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_batched_kernel(
     uint32_t n_items, unsigned* __restrict__ counter, const uint64_t* __restrict__ binom,
     int max_M, DeviceStatus* __restrict__ st, int nwin_max) {
   constexpr bool DISP = false;
+  constexpr bool MIXED = false;
   constexpr int rmax = kGroupRmax;
   constexpr int NB = D - 1;
   using GL = GroupLayout<NB, DISP>;
@@ -254,6 +287,10 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_batched_kernel(
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const double* const mi = nullptr;
+  const double* const pk = nullptr;
+  const float* const E = nullptr;
+  const float* const Eodd = nullptr;
+  const uint32_t lde4 = 0;
 
   for (;;) {
     __syncthreads();  // every reader of the previous item index is done
@@ -392,9 +429,9 @@ int group_windows(int M) {
   return (GroupLayout<NB, DISP>::kB * (M - NB) + 63) / 64 + 1;
 }
 
-template <int NB, bool DISP>
+template <int NB, bool DISP, bool MIXED = false>
 size_t group_lds(int M) {
-  using GL = GroupLayout<NB, DISP>;
+  using GL = GroupLayout<NB, DISP, MIXED>;
   const int D = NB + 1;
   return (size_t)GL::kB * GL::bytes + (size_t)kGroupRmax * GL::rbytes +
          (size_t)kGroupG * GL::gbytes +
@@ -402,23 +439,25 @@ size_t group_lds(int M) {
          (size_t)group_windows<NB, DISP>(M) * (sizeof(uint64_t) + 1);
 }
 
-template <bool DISP>
+template <bool DISP, bool MIXED = false>
 size_t group_lds_d(int d, int M) {
   switch (d) {
-    case 3: return group_lds<2, DISP>(M);
-    case 4: return group_lds<3, DISP>(M);
-    default: return group_lds<4, DISP>(M);
+    case 3: return group_lds<2, DISP, MIXED>(M);
+    case 4: return group_lds<3, DISP, MIXED>(M);
+    default: return group_lds<4, DISP, MIXED>(M);
   }
 }
 
 }  // namespace
 
 bool group_supported(int d, int M, int flags, bool displaced) {
-  if (d < 3 || d > kMaxOrder || (flags & GBS_MIXED)) return false;
+  if (d < 3 || d > kMaxOrder || (displaced && (flags & GBS_MIXED))) return false;
   for (int q = 1; q <= d; ++q)
     if (host_binom(M, q) >= (1ull << 29)) return false;
   if (group_rmax(M, d - 1) < 0 || M > 255) return false;
-  const size_t lds = displaced ? group_lds_d<true>(d, M) : group_lds_d<false>(d, M);
+  const size_t lds = displaced ? group_lds_d<true>(d, M)
+                    : (flags & GBS_MIXED) ? group_lds_d<false, true>(d, M)
+                                          : group_lds_d<false>(d, M);
   return lds <= 64 * 1024;
 }
 
@@ -436,10 +475,19 @@ uint32_t group_plan_grid(uint32_t ntiles, int cu_count) {
   return std::min<uint32_t>(ntiles, (uint32_t)std::max(cu_count, 1) * kGroupWgPerCU);
 }
 
-template <int D, int CONV, bool WC, bool DISP>
-static hipError_t launch_group_t(int M, const double* Qi, const double* Qd, const double* mi,
-                                 const uint64_t* binom, const OrderTables& tab, double* m_out,
-                                 double* k_out, double* p_out, DeviceStatus* st, hipStream_t s,
+// The operands of one single-instance launch.
+struct GroupArgs {
+  const double* Qi;
+  const double* Qd;
+  const double* mi;
+  const double* pk;
+  const float* E;
+};
+
+template <int D, int CONV, bool WC, bool DISP, bool MIXED>
+static hipError_t launch_group_t(int M, const GroupArgs& g, const uint64_t* binom,
+                                 const OrderTables& tab, double* m_out, double* k_out,
+                                 double* p_out, DeviceStatus* st, hipStream_t s,
                                  const GroupPlanRef* ext) {
   constexpr int NB = D - 1;
   if (host_binom(M, D) == 0) return hipSuccess;
@@ -454,42 +502,47 @@ static hipError_t launch_group_t(int M, const double* Qi, const double* Qd, cons
   }
   if (plan.ntiles == 0) return hipSuccess;
   const int nwin = group_windows<NB, DISP>(M);
-  const size_t lds = group_lds<NB, DISP>(M);
-  hipLaunchKernelGGL((forward_group_kernel<D, CONV, WC, DISP>), dim3(plan.grid),
-                     dim3(kGroupThreads), lds, s, Qi, Qd, mi, M, plan.dev, plan.ntiles, binom, tab,
-                     m_out, k_out, p_out, st, nwin);
+  const size_t lds = group_lds<NB, DISP, MIXED>(M);
+  hipLaunchKernelGGL((forward_group_kernel<D, CONV, WC, DISP, MIXED>), dim3(plan.grid),
+                     dim3(kGroupThreads), lds, s, g.Qi, g.Qd, g.mi, g.pk, g.E, M, plan.dev,
+                     plan.ntiles, binom, tab, m_out, k_out, p_out, st, nwin);
   return hipGetLastError();
 }
 
-template <int D, int CONV, bool DISP>
-static hipError_t launch_group_w(int M, const double* Qi, const double* Qd, const double* mi,
-                                 const uint64_t* binom, const OrderTables& tab, double* m_out,
-                                 double* k_out, double* p_out, DeviceStatus* st, hipStream_t s,
+template <int D, int CONV, bool DISP, bool MIXED>
+static hipError_t launch_group_w(int M, const GroupArgs& g, const uint64_t* binom,
+                                 const OrderTables& tab, double* m_out, double* k_out,
+                                 double* p_out, DeviceStatus* st, hipStream_t s,
                                  const GroupPlanRef* ext) {
   if (k_out)
-    return launch_group_t<D, CONV, true, DISP>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st,
-                                               s, ext);
-  return launch_group_t<D, CONV, false, DISP>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st,
-                                              s, ext);
+    return launch_group_t<D, CONV, true, DISP, MIXED>(M, g, binom, tab, m_out, k_out, p_out, st,
+                                                      s, ext);
+  return launch_group_t<D, CONV, false, DISP, MIXED>(M, g, binom, tab, m_out, k_out, p_out, st, s,
+                                                     ext);
+}
+
+template <int D, int CONV>
+static hipError_t launch_group_v(int M, int flags, const GroupArgs& g, const uint64_t* binom,
+                                 const OrderTables& tab, double* m_out, double* k_out,
+                                 double* p_out, DeviceStatus* st, hipStream_t s,
+                                 const GroupPlanRef* ext) {
+  // displaced states plan their own (narrower) tiles
+  if (g.mi)
+    return launch_group_w<D, CONV, true, false>(M, g, binom, tab, m_out, k_out, p_out, st, s,
+                                                nullptr);
+  if (flags & GBS_MIXED)
+    return launch_group_w<D, CONV, false, true>(M, g, binom, tab, m_out, k_out, p_out, st, s, ext);
+  return launch_group_w<D, CONV, false, false>(M, g, binom, tab, m_out, k_out, p_out, st, s, ext);
 }
 
 template <int D>
-static hipError_t launch_group_c(int M, int flags, const double* Qi, const double* Qd,
-                                 const double* mi, const uint64_t* binom, const OrderTables& tab,
-                                 double* m_out, double* k_out, double* p_out, DeviceStatus* st,
-                                 hipStream_t s, const GroupPlanRef* ext) {
-  if (flags & GBS_PARITY) {
-    if (mi)
-      return launch_group_w<D, GBS_PARITY, true>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out,
-                                                 st, s, nullptr);
-    return launch_group_w<D, GBS_PARITY, false>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out,
-                                                st, s, ext);
-  }
-  if (mi)
-    return launch_group_w<D, GBS_CLICK, true>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st,
-                                              s, nullptr);
-  return launch_group_w<D, GBS_CLICK, false>(M, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s,
-                                             ext);
+static hipError_t launch_group_c(int M, int flags, const GroupArgs& g, const uint64_t* binom,
+                                 const OrderTables& tab, double* m_out, double* k_out,
+                                 double* p_out, DeviceStatus* st, hipStream_t s,
+                                 const GroupPlanRef* ext) {
+  if (flags & GBS_PARITY)
+    return launch_group_v<D, GBS_PARITY>(M, flags, g, binom, tab, m_out, k_out, p_out, st, s, ext);
+  return launch_group_v<D, GBS_CLICK>(M, flags, g, binom, tab, m_out, k_out, p_out, st, s, ext);
 }
 
 void group_tiles(int d, int M, std::vector<uint64_t>* out) {
@@ -571,13 +624,16 @@ hipError_t launch_group_batched(int d, int flags, const GroupBatchInstance* inst
 }
 
 hipError_t launch_forward_group(int d, int M, int flags, const double* Qi, const double* Qd,
-                                const double* mi, const uint64_t* binom, const OrderTables& tab,
-                                double* m_out, double* k_out, double* p_out, DeviceStatus* st,
-                                hipStream_t s, const GroupPlanRef* plan) {
+                                const double* mi, const double* pk, const float* E,
+                                const uint64_t* binom, const OrderTables& tab, double* m_out,
+                                double* k_out, double* p_out, DeviceStatus* st, hipStream_t s,
+                                const GroupPlanRef* plan) {
+  if (mi && (flags & GBS_MIXED)) return hipErrorInvalidValue;
+  const GroupArgs g{Qi, Qd, mi, pk, E};
   switch (d) {
-    case 3: return launch_group_c<3>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s, plan);
-    case 4: return launch_group_c<4>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s, plan);
-    case 5: return launch_group_c<5>(M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s, plan);
+    case 3: return launch_group_c<3>(M, flags, g, binom, tab, m_out, k_out, p_out, st, s, plan);
+    case 4: return launch_group_c<4>(M, flags, g, binom, tab, m_out, k_out, p_out, st, s, plan);
+    case 5: return launch_group_c<5>(M, flags, g, binom, tab, m_out, k_out, p_out, st, s, plan);
     default: return hipErrorInvalidValue;
   }
 }

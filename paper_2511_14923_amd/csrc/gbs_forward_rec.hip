@@ -526,8 +526,8 @@ hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const d
   }
   // the tile kernel takes zero-mean states only
   if (group_supported(d, M, flags, mi != nullptr))
-    return launch_forward_group(d, M, flags, Qi, Qd, mi, binom, tab, m_out, k_out, p_out, st, s,
-                                (plans && !mi) ? &plans[d] : nullptr);
+    return launch_forward_group(d, M, flags, Qi, Qd, mi, pk, E, binom, tab, m_out, k_out, p_out, st,
+                                s, (plans && !mi) ? &plans[d] : nullptr);
   if (!mi && tile_supported(d, M, flags))
     return launch_forward_tile(d, M, flags, Qi, Qd, binom, tab, m_out, k_out, p_out, st, s);
   switch (d) {

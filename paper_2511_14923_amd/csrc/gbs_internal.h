@@ -97,7 +97,7 @@ hipError_t launch_forward_tile(int d, int M, int flags, const double* Qi, const 
                                const uint64_t* binom, const OrderTables& tab, double* m_out,
                                double* k_out, double* p_out, DeviceStatus* st, hipStream_t s);
 
-// Group-tiled FP64 kernel of order d (3..5), the default where it applies:
+// Group-tiled kernel of order d (3..5), FP64 or mixed, the default where it applies:
 // 32-bit ranks and LDS for (M - d + 1) records per tile; see
 // gbs_forward_group.hip.  Tile plans are built on the host once per (M, d,
 // tile width) and kept on the device until the process ends.  mi: interleaved
@@ -117,9 +117,10 @@ struct GroupPlanRef {
 const std::vector<uint64_t>& group_plan_host(int d, int M);
 uint32_t group_plan_grid(uint32_t ntiles, int cu_count);
 hipError_t launch_forward_group(int d, int M, int flags, const double* Qi, const double* Qd,
-                                const double* mi, const uint64_t* binom, const OrderTables& tab,
-                                double* m_out, double* k_out, double* p_out, DeviceStatus* st,
-                                hipStream_t s, const GroupPlanRef* plan = nullptr);
+                                const double* mi, const double* pk, const float* E,
+                                const uint64_t* binom, const OrderTables& tab, double* m_out,
+                                double* k_out, double* p_out, DeviceStatus* st, hipStream_t s,
+                                const GroupPlanRef* plan = nullptr);
 
 // The group kernel over many zero-mean instances: one persistent launch per
 // order claims (instance, tile) items from a device work list.  Instance i of

@@ -29,7 +29,7 @@ struct NoAllocDevice {
   bool ready = false;
   char* base = nullptr;  // device address of this device's `scratch`
   int cu_count = 0;
-  // layout of the last call whose tile plans are in place (M, max_order), or 0
+  // layout of the last call whose tile plans are in place (M, max_order, mixed), or 0
   uint64_t plan_key = 0;
 };
 
@@ -144,7 +144,10 @@ extern "C" GBS_API gbs_status gbs_cumulants_noalloc(int32_t M, const double* sig
     any_plan = true;
   }
   {
-    const uint64_t key = any_plan ? ((uint64_t)M << 8 | (uint64_t)max_order) : 0;
+    // the plans' offsets depend on M, max_order and the mixed operands before them
+    const uint64_t key =
+        any_plan ? ((uint64_t)M << 8 | (uint64_t)max_order << 1 | ((flags & GBS_MIXED) ? 1 : 0))
+                 : 0;
     std::lock_guard<std::mutex> lock(g_noalloc_mu);
     if (any_plan && D->plan_key != key) {
       for (int d = 3; d <= max_order && e == hipSuccess; ++d) {
