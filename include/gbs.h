@@ -72,8 +72,9 @@ enum {
     GBS_CLICK = 0,   /* bit 0 clear: click correlators mu and click cumulants kappa~ (default) */
     GBS_PARITY = 1,  /* bit 0 set:   parity correlators c and cumulants kappa                  */
     GBS_FP64 = 0,    /* bit 1 clear: every step in FP64 (default)                              */
-    GBS_MIXED = 2,   /* bit 1 set:   FP32 determinant work on a normalised Q, FP64 compensated
-                        inclusion-exclusion and partition sums (not for gbs_cumulant_grad)     */
+    GBS_MIXED = 2,   /* bit 1 set:   FP32 determinant work on the normalised Q (deviations from
+                        the identity), FP64 probabilities, inclusion-exclusion and partition
+                        sums (not for gbs_cumulant_grad); error per order as reported       */
     GBS_ASYNC = 4,   /* bit 2 set:   return right after the launches; a NOT_SPD pivot is then
                         reported only by gbs_last_error after the stream has completed          */
     GBS_TIMING = 8,  /* bit 3 set:   record a HIP event pair around every kernel launch of the

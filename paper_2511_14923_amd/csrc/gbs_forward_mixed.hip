@@ -1,4 +1,9 @@
-// Mixed-precision forward kernel: FP32 determinant work, FP64 sums.
+// Mixed-precision all-minors kernel: FP32 determinant work, FP64 sums.  It
+// runs for GBS_MIXED | GBS_ALL_MINORS (evaluating all 2^d minors of every
+// subset, no lower-order tables); the default mixed path is the group kernel
+// (gbs_forward_group.hip) with the same normalisation and deviation form in
+// its shared factors and plain FP64 sums, and the order-recursive kernel's
+// mixed branch for orders 1 and 2.
 //
 // Normalisation (per mode, FP64): Q_kk = L_k L_k^T (2x2 Cholesky), the
 // single-mode vacuum probability p_k = det(Q_kk)^(-1/2), and the normalised
