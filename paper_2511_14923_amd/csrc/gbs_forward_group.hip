@@ -122,7 +122,12 @@ struct GroupLayout {
   static constexpr int uS = uT + (MIXED ? 1 : 2);       // Schur complement of Q_P in Q_{P + a}: s00, s10, s11
   static constexpr int uPK = uS + (MIXED ? 1 : 2);      // mixed: p_a = det(Q_aa)^(-1/2) (FP64)
   static constexpr int uPT = uPK + (MIXED ? 1 : 0);     // nu, nue of the W subset of P (FP64)
-  static constexpr int rUnits = uPT + (NTS + 1) / 2;
+  // mixed (whose records leave LDS room): the cumulants k({a} + W + e), W
+  // subset of P, of the recursion's b_0-free half, one FP64 each
+  static constexpr bool KLO = MIXED;
+  static constexpr int NPS = NTS / 2;                   // subsets of P
+  static constexpr int uKL = uPT + (NTS + 1) / 2;
+  static constexpr int rUnits = uKL + (KLO ? (NPS + 1) / 2 : 0);
   static constexpr int rbytes = rUnits * 16;    // per record
   // per-group record (Cholesky of Q_T in the order P, e), doubles
   static constexpr int gP = 0;                  // L_P: tri(i, j), 1/L_ii on the diagonal
@@ -225,6 +230,7 @@ __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(1
   __shared__ uint32_t s_ntile, s_r0, s_ngroups, s_nrec;
   __shared__ uint32_t s_gbase[kGroupG];      // first (T, a) record of each group
   __shared__ int s_gT[kGroupG][NB - 1];       // modes of T, in the order P, e
+  __shared__ int s_gc[kGroupG];               // record slot of a non-empty B of each group
 
   for (int i = threadIdx.x; i < (D + 1) * ld; i += blockDim.x) {
     const int kk = i / ld, nn = i - kk * ld;
@@ -278,6 +284,7 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_batched_kernel(
   __shared__ uint32_t s_ntile, s_r0, s_ngroups, s_nrec;
   __shared__ uint32_t s_gbase[kGroupG];
   __shared__ int s_gT[kGroupG][NB - 1];
+  __shared__ int s_gc[kGroupG];
   __shared__ uint32_t s_item;
 
   for (int i = threadIdx.x; i < (D + 1) * ld; i += blockDim.x) {
