@@ -60,13 +60,17 @@ constexpr int kGroupRmax = 148;     // (T, a) records per tile at most (M - d + 
 // per tile, ~430,000 tiles).
 constexpr uint32_t kGroupWgPerCU = 192;
 // Tile descriptor (64 bits): the colex rank of the tile's first B (29 bits),
-// the number of B's (6 bits), and the modes of that B's T (8 bits each), so
-// that each lane finds its B by walking the groups from the first one instead
-// of unranking.  The group kernel runs only where every rank fits in 29 bits
-// and M <= 152 (group_supported).
+// the number of B's (7 bits), and the modes of that B's T (8 bits each, at most
+// three), so that each lane finds its B by walking the groups from the first
+// one instead of unranking.  The group kernel runs only where every rank fits
+// in 29 bits and M <= 152 (group_supported).
 constexpr int kDescNbShift = 29;
-constexpr int kDescTShift = 35;
+constexpr int kDescNbBits = 7;
+constexpr int kDescTShift = kDescNbShift + kDescNbBits;
 constexpr uint64_t kDescBetaMask = (1ull << kDescNbShift) - 1;
+constexpr uint64_t kDescNbMask = (1ull << kDescNbBits) - 1;
+static_assert(kGroupB <= (int)kDescNbMask, "the B count of a tile must fit its descriptor field");
+static_assert(kDescTShift + 3 * 8 <= 64, "the descriptor holds three 8-bit modes");
 // steps of a lane's walk at most: the groups of a tile (kGroupG) and the empty
 // T (min T = 0) between them, at most two per group
 constexpr int kWalkMax = 3 * kGroupG + 4;
@@ -336,9 +340,9 @@ std::vector<uint64_t> plan_tiles(int M, int NB, int rmax, int kB) {
   uint64_t tfirst = 0;  // modes of the T of the tile's first B, 8 bits each
   int nB = 0, rec = 0, ng = 0;
   auto close = [&]() {
-    if (nB > 0)
-      tiles.push_back((uint64_t)tstart | ((uint64_t)nB << kDescNbShift) |
-                      (tfirst << kDescTShift));
+    if (nB > 0)  // never an empty tile; every field within its width
+      tiles.push_back(((uint64_t)tstart & kDescBetaMask) |
+                      (((uint64_t)nB & kDescNbMask) << kDescNbShift) | (tfirst << kDescTShift));
     nB = 0;
     rec = 0;
     ng = 0;
