@@ -224,6 +224,159 @@ def batched_and_adjoint(P, torch, G, steps):
     return out
 
 
+def config_lines(P, torch, np, G, steps):
+    """Throughput on the two smaller plain-FP64 workloads (M = 16, K = 3 and
+    M = 100, K = 4) with the C oracle timed on the identical workload, and the
+    gradient workload (M = 144, K = 3): the adjoint against the oracle's
+    gradient and against central differences (h = 1e-6) of the GPU loss in all
+    288 parameters (576 forward evaluations), each timed."""
+    import oracle as O
+    out = {}
+    for name, K_ in (("m16_k3", 3), ("m100_k4", 4)):
+        inst = G.make_instance(name)
+        M_ = inst.M
+        s = torch.from_numpy(inst.sigma).to("cuda:0")
+        n = P.gbs_total_outputs(M_, K_)
+        corr = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        cum = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        for _ in range(3):
+            P.gbs_cumulants(M_, s, K_, 0, corr=corr, cum=cum)
+        reps = max(steps, 20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P.gbs_cumulants(M_, s, K_, P.GBS_ASYNC, corr=corr, cum=cum)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        st, _, _ = P.gbs_last_error()
+        if st != P.GBS_OK:
+            raise P.GBSError(st, name)
+        t1 = time.perf_counter()
+        rc, rk = O.c_forward(inst.sigma, K_)
+        dto = time.perf_counter() - t1
+        gc, gk = corr.cpu().numpy(), cum.cpu().numpy()
+        worst = 0.0
+        for d in range(1, K_ + 1):
+            a, b = O.order_offset(M_, d), O.order_offset(M_, d + 1)
+            ranks = np.arange(b - a, dtype=np.int64)
+            smu, spi = O.c_tolerance_scale(inst.sigma, d, ranks)
+            _, vk = O.c_error_floor(inst.sigma, d, ranks)
+            worst = max(worst, float(np.max(np.abs(gc[a:b] - rc[a:b]) / fp64_tolerance(np, rc[a:b], smu))),
+                        float(np.max(np.abs(gk[a:b] - rk[a:b]) / fp64_tolerance(np, rk[a:b], spi, vk))))
+        out[name] = {"M": M_, "max_order": K_, "subsets": n, "ms_per_call": 1e3 * dt,
+                     "subsets_per_s": n / dt,
+                     "cpu_oracle": {"seconds": dto, "subsets_per_s": n / dto,
+                                    "cores": O.c_threads(0), "kind": "oracle",
+                                    "sample": "the whole workload"},
+                     "worst_err_over_tol_all_outputs": worst}
+        log(f"[bench] {name}: {1e3 * dt:.3f} ms per call, oracle {dto:.2f} s, worst err/tol {worst:.3g}")
+    # gradient workload: adjoint vs the oracle's gradient and finite differences
+    from paper_2511_14923_amd import autograd as A
+    inst = G.make_instance("grad_m144_k3")
+    _, _, sig_t = G.make_grad_target(inst)
+    _, target = O.c_forward(sig_t, 3)
+    t1 = time.perf_counter()
+    loss_ref, gsig_ref = O.c_loss_grad(inst.sigma, 3, target)
+    t_oracle = time.perf_counter() - t1
+    d_eta, d_r = O.covariance_param_grad(inst.U, inst.r, inst.eta, gsig_ref)
+    ref = np.concatenate([d_eta, d_r])
+    W = A.interferometer_symplectic(torch.from_numpy(inst.U).to("cuda:0"))
+    r = torch.tensor(inst.r, device="cuda:0", requires_grad=True)
+    eta = torch.tensor(inst.eta, device="cuda:0", requires_grad=True)
+    tgt = torch.from_numpy(target).to("cuda:0")
+    loss = A.cumulant_matching_loss(W, r, eta, tgt, 3)
+    loss.backward()
+    got = np.concatenate([eta.grad.cpu().numpy(), r.grad.cpu().numpy()])
+    h = 1e-6
+    fd = np.empty(288)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    with torch.no_grad():
+        for i in range(288):
+            e = torch.zeros(288, dtype=torch.float64, device="cuda:0")
+            e[i] = h
+            lp = A.cumulant_matching_loss(W, r + e[144:], eta + e[:144], tgt, 3)
+            lm = A.cumulant_matching_loss(W, r - e[144:], eta - e[:144], tgt, 3)
+            fd[i] = float((lp - lm) / (2 * h))
+    t_fd = time.perf_counter() - t1
+
+    def normwise(a, b):
+        return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+    out["grad_m144_k3_checks"] = {
+        "params": 288, "loss": float(loss.detach()), "loss_oracle": loss_ref,
+        "adjoint_vs_oracle_normwise": normwise(got, ref),
+        "adjoint_vs_fd_normwise": normwise(got, fd),
+        "oracle_gradient_seconds": t_oracle, "oracle_cores": O.c_threads(0),
+        "fd_forward_evaluations": 576, "fd_seconds": t_fd}
+    log(f"[bench] gradient: oracle {t_oracle:.2f} s, 576 FD evaluations {t_fd:.2f} s, "
+        f"adjoint vs oracle {out['grad_m144_k3_checks']['adjoint_vs_oracle_normwise']:.2e}, "
+        f"vs FD {out['grad_m144_k3_checks']['adjoint_vs_fd_normwise']:.2e}")
+    return out
+
+
+def full_parity(np, O, inst, bufs, chunk=8_000_000):
+    """Every output of the M = 144, K = 5 workload against the C oracle, streamed
+    in rank blocks: the FP64 form to its tolerance (the carried-in term is
+    computed only for the outputs outside 1e-10 max(|ref|, 1e-4 S_pi)), the
+    mixed form's relative error per order.  Returns the oracle's time on the
+    whole workload (with the tolerance scales) and the worst ratios."""
+    threads = O.c_threads(0)
+    res = {"cores": threads, "orders": {}}
+    t_all = 0.0
+    worst = 0.0
+    for d in range(1, K + 1):
+        cnt = math.comb(M, d)
+        off = O.order_offset(M, d)
+        od = {"outputs": cnt, "worst_corr_err_over_tol": 0.0, "worst_cum_err_over_tol": 0.0,
+              "carried_term_needed": 0}
+        mixed_num = {"corr": 0.0, "cum": 0.0}
+        mixed_den = {"corr": 0.0, "cum": 0.0}
+        rel_all = []
+        for r0 in range(0, cnt, chunk):
+            n = min(chunk, cnt - r0)
+            t0 = time.perf_counter()
+            rc, rk, smu, spi = O.c_forward_range(inst.sigma, d, r0, n, scales=True, threads=threads)
+            t_all += time.perf_counter() - t0
+            gc = bufs["fp64"][0][off + r0: off + r0 + n].cpu().numpy()
+            gk = bufs["fp64"][1][off + r0: off + r0 + n].cpu().numpy()
+            ec = np.abs(gc - rc) / fp64_tolerance(np, rc, smu)
+            od["worst_corr_err_over_tol"] = max(od["worst_corr_err_over_tol"], float(ec.max()))
+            cheap = fp64_tolerance(np, rk, spi)
+            ek = np.abs(gk - rk)
+            out_idx = np.nonzero(ek > cheap)[0]
+            ratio = ek / cheap
+            if len(out_idx):
+                od["carried_term_needed"] += int(len(out_idx))
+                ranks = (r0 + out_idx).astype(np.int64)
+                _, vk = O.c_error_floor(inst.sigma, d, ranks, threads=threads)
+                ratio[out_idx] = ek[out_idx] / fp64_tolerance(np, rk[out_idx], spi[out_idx], vk)
+            od["worst_cum_err_over_tol"] = max(od["worst_cum_err_over_tol"], float(ratio.max()))
+            worst = max(worst, float(ec.max()), float(ratio.max()))
+            if "mixed" in bufs:
+                mc = bufs["mixed"][0][off + r0: off + r0 + n].cpu().numpy()
+                mk = bufs["mixed"][1][off + r0: off + r0 + n].cpu().numpy()
+                mixed_num["corr"] = max(mixed_num["corr"], float(np.abs(mc - rc).max()))
+                mixed_num["cum"] = max(mixed_num["cum"], float(np.abs(mk - rk).max()))
+                mixed_den["corr"] = max(mixed_den["corr"], float(np.abs(rc).max()))
+                mixed_den["cum"] = max(mixed_den["cum"], float(np.abs(rk).max()))
+                rel_all.append((np.abs(mk - rk) / np.maximum(np.abs(rk), 1e-300))[:: max(1, n // 200000)])
+            if (r0 // chunk) % 10 == 0:
+                log(f"[bench] full parity: order {d}, ranks {r0 + n}/{cnt}, oracle {t_all:.0f} s")
+        if rel_all:
+            rel = np.concatenate(rel_all)
+            od["mixed_vs_oracle"] = {
+                "corr_normwise": mixed_num["corr"] / mixed_den["corr"],
+                "cum_normwise": mixed_num["cum"] / mixed_den["cum"],
+                "cum_rel_median": float(np.median(rel)), "cum_rel_p99": float(np.quantile(rel, 0.99)),
+                "cum_rel_max_sampled": float(rel.max())}
+        res["orders"][str(d)] = od
+    res["oracle_seconds_all_outputs"] = t_all
+    res["oracle_subsets_per_s"] = sum(math.comb(M, d) for d in range(1, K + 1)) / t_all
+    res["worst_err_over_tol"] = worst
+    return res
+
+
 def sampler_terms(M_, K_):
     """Expansion terms one sample evaluates (the sums of Eqs. methprob, b, a for
     K = 3; Eqs. probade, probpartialade, probelidedade, probdoubleelidedade for
@@ -392,8 +545,9 @@ def cpu_baseline(np, O, G, inst, seconds):
                 done += len(np.unique(sel))
         return done, time.perf_counter() - t0
 
-    n0, t0 = run(20000, 1)
-    n = int(min(5e7, max(20000, n0 / max(t0, 1e-3) * seconds)))
+    # calibrate on a sample large enough that thread start-up does not skew the rate
+    n0, t0 = run(500000, 1)
+    n = int(min(1e8, max(20000, n0 / max(t0, 1e-3) * seconds)))
     done, t = run(n, 2)
     log(f"[bench] cpu oracle: {done} subsets in {t:.2f} s on {threads} threads")
     return {"value": done / t, "unit": "subsets/s", "cores": threads, "kind": "oracle",
@@ -414,6 +568,8 @@ def main():
     ap.add_argument("--all-minors", action="store_true",
                     help="also measure the all-minors kernel (GBS_ALL_MINORS) of both precisions")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--full-parity", action="store_true",
+                    help="compare every output of the workload with the C oracle (minutes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -501,8 +657,11 @@ def main():
             extra["displaced_worst_err_over_tol"] = fp64_parity_sample(
                 np, O, G, inst, cd, kd, mu=G.input_displacement(inst))
             del cd, kd
+    if args.full_parity:
+        extra["full_parity"] = full_parity(np, __import__("oracle"), inst, bufs)
     if not args.no_extras and not args.only:
         extra["extras"] = batched_and_adjoint(P, torch, G, 5)
+        extra["extras"].update(config_lines(P, torch, np, G, args.steps))
         for form in list(bufs):
             del bufs[form]
         torch.cuda.empty_cache()
