@@ -181,25 +181,34 @@ def batched_and_adjoint(P, torch, G, steps):
                      torch.empty(n, dtype=torch.float64, device="cuda:0")))
         n_sub += n
         flops += sum(math.comb(inst.M, d) * FLOPS_PER_SUBSET[d] for d in range(1, 5))
-    P.gbs_cumulants_batched(bufs, 4, 0)  # plan, graph capture
-    torch.cuda.synchronize()
-    walls, kern = [], []
-    for _ in range(steps):
+    for label, fl in (("batched48_k4", 0), ("batched48_k4_mixed", P.GBS_MIXED)):
+        # launch shapes from the autotuner (all-minors shape, then the group
+        # launches' workgroups per CU), cached in the library for later calls
         t0 = time.perf_counter()
-        P.gbs_cumulants_batched(bufs, 4, 0)
+        tuned = P.gbs_autotune_batched(bufs, 4, fl)
+        t_tune = time.perf_counter() - t0
+        P.gbs_cumulants_batched(bufs, 4, fl)  # plan, graph capture
         torch.cuda.synchronize()
-        walls.append(time.perf_counter() - t0)
-        P.gbs_cumulants_batched(bufs, 4, P.GBS_TIMING)
-        kern.append(sum(ms for st, _, ms in P.gbs_last_timings() if st == "batched"))
-    wall = sorted(walls)[len(walls) // 2]
-    kms = sorted(kern)[len(kern) // 2]
-    out["batched48_k4"] = {
-        "instances": len(batch), "subsets": n_sub, "ms_per_call": 1e3 * wall,
-        "subsets_per_s": n_sub / wall, "kernel_ms": kms,
-        "kernel_tflops": flops / (kms * 1e-3) / 1e12,
-        "frac_of_fp64_peak": flops / (kms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS,
-        "kernel": ("persistent work lists: orders 1-2 all-minors, orders 3-4 the group "
-                   "kernel, one launch per order")}
+        walls, kern = [], []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            P.gbs_cumulants_batched(bufs, 4, fl)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+            P.gbs_cumulants_batched(bufs, 4, fl | P.GBS_TIMING)
+            kern.append(sum(ms for st, _, ms in P.gbs_last_timings() if st == "batched"))
+        wall = sorted(walls)[len(walls) // 2]
+        kms = sorted(kern)[len(kern) // 2]
+        out[label] = {
+            "instances": len(batch), "subsets": n_sub, "ms_per_call": 1e3 * wall,
+            "subsets_per_s": n_sub / wall, "kernel_ms": kms,
+            "kernel_tflops": flops / (kms * 1e-3) / 1e12,
+            "frac_of_fp64_peak": flops / (kms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS,
+            "tuned_shape": tuned, "autotune_seconds": t_tune,
+            "kernel": ("persistent work lists: orders 1-2 all-minors, orders 3-4 the group "
+                       "kernel, one launch per order" if fl == 0 else
+                       "persistent work list: every order all-minors (normalised FP32 minors)")}
+        log(f"[bench] {label}: {1e3 * wall:.2f} ms per call, kernels {kms:.2f} ms, tuned {tuned}")
     del bufs
     inst = G.make_instance("grad_m144_k3")
     s = torch.from_numpy(inst.sigma).to("cuda:0")

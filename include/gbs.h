@@ -279,18 +279,24 @@ typedef struct {
 GBS_API gbs_status gbs_cumulants_batched(int32_t n, const gbs_instance* inst, int32_t max_order,
                                  int32_t flags, void* stream);
 
-/* Launch shape of the batched all-minors launch. */
+/* Launch shape of the batched launches: the all-minors launch (block, unroll,
+ * tile, waves_per_cu) and the group launches (group_wpc). */
 typedef struct {
     int32_t block;   /* threads per workgroup: 64, 128 or 256               */
     int32_t unroll;  /* subsets per thread and work item: 1, 2 or 4         */
     int32_t tile;    /* subsets per work item (multiple of block * unroll)  */
     int32_t waves_per_cu; /* persistent workgroups per compute unit, 1..8   */
+    int32_t group_wpc; /* workgroups per compute unit of the group launches
+                          (orders 3..K, FP64): 0 = as many as fit, else 1..8 */
 } gbs_tuning;
 
 /* Launch-shape autotuner of gbs_cumulants_batched (library plumbing, not in the
- * paper).  Times every candidate shape on the given batch (outputs are overwritten,
- * stream-ordered, synchronising) and caches the fastest for this device,
- * order and precision; writes it to *best (host) when best is non-NULL. */
+ * paper).  Times the whole pipeline on the given batch for every candidate
+ * shape of the all-minors launch (81: block x unroll x tile x workgroups per
+ * CU), then, with the fastest, for the group launches' workgroups per CU
+ * (as many as fit, 2, 1); outputs are overwritten (stream-ordered,
+ * synchronising).  Caches the fastest shape for this device, order and
+ * precision; writes it to *best (host) when best is non-NULL. */
 GBS_API gbs_status gbs_autotune_batched(int32_t n, const gbs_instance* inst, int32_t max_order,
                                 int32_t flags, void* stream, gbs_tuning* best);
 

@@ -68,7 +68,7 @@ class gbs_instance(ctypes.Structure):
 
 class gbs_tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("unroll", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("waves_per_cu", ctypes.c_int32)]
+                ("waves_per_cu", ctypes.c_int32), ("group_wpc", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -224,13 +224,13 @@ struct TuneKey {
 std::mutex g_tune_mutex;
 std::map<TuneKey, gbs_tuning> g_tuning;
 
-gbs_tuning default_tuning() { return gbs_tuning{256, 1, 65536, 2}; }
+gbs_tuning default_tuning() { return gbs_tuning{256, 1, 65536, 2, 0}; }
 
 bool valid_tuning(const gbs_tuning& t) {
   const bool blk = t.block == 64 || t.block == 128 || t.block == 256;
   const bool unr = t.unroll == 1 || t.unroll == 2 || t.unroll == 4;
   return blk && unr && t.tile >= t.block * t.unroll && t.tile % (t.block * t.unroll) == 0 &&
-         t.waves_per_cu >= 1 && t.waves_per_cu <= 8;
+         t.waves_per_cu >= 1 && t.waves_per_cu <= 8 && t.group_wpc >= 0 && t.group_wpc <= 8;
 }
 
 gbs_tuning lookup_tuning(int device, int K, int flags) {
@@ -301,7 +301,7 @@ bool same_key(const BatchPlan* p, int dev, hipStream_t s, int n, const gbs_insta
       (int)p->key.size() != n)
     return false;
   if (p->tuning.block != t.block || p->tuning.unroll != t.unroll || p->tuning.tile != t.tile ||
-      p->tuning.waves_per_cu != t.waves_per_cu)
+      p->tuning.waves_per_cu != t.waves_per_cu || p->tuning.group_wpc != t.group_wpc)
     return false;
   return std::memcmp(p->key.data(), inst, sizeof(gbs_instance) * n) == 0;
 }
@@ -470,6 +470,7 @@ gbs_status build_plan(BatchPlan* p, int n, const gbs_instance* inst, int K, int 
     p->g_lds[d] = group_batched_lds(d, p->g_max_M[d], &p->g_nwin[d]);
     e = group_batched_grid(d, flags, p->g_lds[d], ctx->cu_count, &p->g_grid[d]);
     if (e != hipSuccess) return to_status(e);
+    if (t.group_wpc > 0) p->g_grid[d] = std::min(p->g_grid[d], ctx->cu_count * t.group_wpc);
   }
   e = hipMalloc(&p->mem, bytes);
   if (e != hipSuccess) return to_status(e);
@@ -601,20 +602,20 @@ gbs_status run_autotune(int n, const gbs_instance* inst, int K, int flags, void*
     for (int unroll : {1, 2, 4})
       for (int tile_mult : {16, 64, 256})
         for (int wpc : {1, 2, 4})
-          cands.push_back(gbs_tuning{block, unroll, block * unroll * tile_mult, wpc});
+          cands.push_back(gbs_tuning{block, unroll, block * unroll * tile_mult, wpc, 0});
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return GBS_E_DEVICE;
   float best_ms = 1e30f;
   gbs_tuning best = default_tuning();
   gbs_status result = GBS_OK;
-  for (const gbs_tuning& t : cands) {
+  // the whole pipeline with shape t, three timed runs after a warm-up
+  auto try_shape = [&](const gbs_tuning& t) -> gbs_status {
     BatchPlan plan;
     gbs_status st =
         build_plan(&plan, n, inst, K, flags & (GBS_PARITY | GBS_MIXED | GBS_ALL_MINORS), t);
     if (st != GBS_OK) {
       plan.release();
-      result = st;
-      break;
+      return st;
     }
     float total = 0.f;
     e = launch_pipeline(plan, s, false);  // warm-up
@@ -629,14 +630,23 @@ gbs_status run_autotune(int n, const gbs_instance* inst, int K, int flags, void*
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     plan.release();
-    if (e != hipSuccess) {
-      result = to_status(e);
-      break;
-    }
+    if (e != hipSuccess) return to_status(e);
     if (total < best_ms) {
       best_ms = total;
       best = t;
     }
+    return GBS_OK;
+  };
+  // the all-minors launch's shape, then the group launches' workgroups per CU
+  for (const gbs_tuning& t : cands) {
+    result = try_shape(t);
+    if (result != GBS_OK) break;
+  }
+  for (int gw : {2, 1}) {
+    if (result != GBS_OK) break;
+    gbs_tuning t = best;
+    t.group_wpc = gw;
+    result = try_shape(t);
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
