@@ -258,21 +258,25 @@ typedef struct {
  * Many instances of uneven M in persistent launches over device work lists
  * (plus the launches that form every instance's Q): one launch over
  * (instance, order, rank range) items evaluated from all the principal minors
- * of Q_S (orders 1 and 2; every order with GBS_MIXED or GBS_ALL_MINORS, and
- * for instances the group kernel does not take), then, in FP64, one launch per
- * order 3..max_order over the (instance, tile) items of the group kernel, which
- * reads each instance's lower-order tables.  Results agree with n separate
- * gbs_cumulants calls (same flags) to FP64 rounding.  Library-owned scratch
- * per instance list: Q and its diagonal blocks, and, for the group launches,
- * the vacuum probabilities of orders 1..max_order-1 (and their correlators when
- * inst.corr is NULL).  The pipeline is captured once into a HIP graph per
- * (instance list, stream, order, flags, tuning) and replayed on later calls
- * with the same list on the same stream (a plan's work-list counter and status
- * word serve one stream: threads calling on one stream are serialised while
- * they enqueue, a list used on two streams gets two plans, and an evicted plan
- * is freed only after its last call has returned); the all-minors launch takes its block shape and unroll from
- * gbs_autotune_batched's cached choice when one exists for this device, else
- * from a fixed default; the group launches fill the device.
+ * of Q_S (orders 1 and 2; every order with GBS_ALL_MINORS, and for instances
+ * the group kernel does not take), then one launch per order 3..max_order over
+ * the (instance, tile) items of the group kernel (FP64 or GBS_MIXED), which
+ * reads each instance's lower-order tables.  FP64 results agree with n separate
+ * gbs_cumulants calls (same flags) to FP64 rounding; mixed-form results agree
+ * with them within the mixed form's error (its orders 1 and 2 come from all
+ * minors here, from the order-recursive kernels there, with FP32 roundings
+ * taken in other orders).  Library-owned scratch per instance list: Q, its
+ * diagonal blocks and (GBS_MIXED) its normalised form, and, for the group
+ * launches, the vacuum probabilities of orders 1..max_order-1 (and their
+ * correlators when inst.corr is NULL).  The pipeline is captured once into a
+ * HIP graph per (instance list, stream, order, flags, tuning) and replayed on
+ * later calls with the same list on the same stream (a plan's work-list counter
+ * and status word serve one stream: threads calling on one stream are
+ * serialised while they enqueue, a list used on two streams gets two plans, and
+ * an evicted plan is freed only after its last call has returned); the launch
+ * shapes come from gbs_autotune_batched's cached choice when one exists for
+ * this device, order and precision, else from a fixed default (the group
+ * launches then fill the device).
  *   n      1 <= n <= 4096
  *   inst   HOST array of n descriptors (pointers inside are device pointers)
  */
@@ -287,7 +291,7 @@ typedef struct {
     int32_t tile;    /* subsets per work item (multiple of block * unroll)  */
     int32_t waves_per_cu; /* persistent workgroups per compute unit, 1..8   */
     int32_t group_wpc; /* workgroups per compute unit of the group launches
-                          (orders 3..K, FP64): 0 = as many as fit, else 1..8 */
+                          (orders 3..K): 0 = as many as fit, else 1..8    */
 } gbs_tuning;
 
 /* Launch-shape autotuner of gbs_cumulants_batched (library plumbing, not in the

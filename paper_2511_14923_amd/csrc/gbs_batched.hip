@@ -1,11 +1,11 @@
 // Batched forward pass: many covariance instances of uneven M in persistent
 // launches over device work lists.
 //
-// FP64, orders 3..K: the group kernel (gbs_forward_group.hip), one persistent
-// launch per order whose work list holds the (instance, tile) items of every
-// instance at that order; each instance reads the tables of its own lower
-// orders, which the previous launches wrote.  Orders 1 and 2, the mixed form,
-// instances the group kernel does not take (M too large) and GBS_ALL_MINORS:
+// Orders 3..K, FP64 or mixed: the group kernel (gbs_forward_group.hip), one
+// persistent launch per order whose work list holds the (instance, tile) items
+// of every instance at that order; each instance reads the tables of its own
+// lower orders, which the previous launches wrote.  Orders 1 and 2, instances
+// the group kernel does not take (M too large) and GBS_ALL_MINORS:
 // one persistent launch over (instance, order, rank range) items, longest
 // first, each subset evaluated from all its minors (no tables needed), which
 // also stores the tables the group launches read.  In every launch a fixed grid
@@ -16,8 +16,9 @@
 //
 // The pipeline (counter and status reset, Q of every instance, diagonal blocks
 // or normalisation, the persistent launches) is captured once into a HIP graph
-// per instance list and replayed; the all-minors launch shape comes from the
-// autotuner's cache, the group launches fill the device.
+// per instance list and replayed; the launch shapes come from the autotuner's
+// cache (the group launches fill the device unless it caps their workgroups
+// per compute unit).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -143,7 +144,7 @@ __device__ __forceinline__ void process_item(const BatchInstance& I, const WorkI
         bool bad = false;
         double pS = 0.0;
         if constexpr (MIXED) {
-          subset_mixed<D, CONV, true>(I.pk, I.E, I.M, s, mS, kS, bad);
+          subset_mixed<D, CONV, true>(I.pk, I.E, I.M, s, mS, kS, pS, bad);
         } else {
           subset_fp64<D, CONV, true>(I.Qi, I.M, s, mS, kS, pS, bad);
         }
@@ -152,7 +153,7 @@ __device__ __forceinline__ void process_item(const BatchInstance& I, const WorkI
         if (I.corr) I.corr[o] = mS;
         else if (I.mtab && D < I.K) I.mtab[o] = mS;
         I.cum[o] = kS;
-        if (!MIXED && I.ptab && D < I.K) I.ptab[o] = pS;
+        if (I.ptab && D < I.K) I.ptab[o] = pS;
       }
     }
   }
@@ -307,10 +308,10 @@ bool same_key(const BatchPlan* p, int dev, hipStream_t s, int n, const gbs_insta
 }
 
 // Order d of an instance of M modes runs on the group kernel (reading the
-// tables of its lower orders) unless the call asks for all minors or the mixed
-// form, or the group kernel does not take that (d, M).
+// tables of its lower orders) unless the call asks for all minors or the group
+// kernel does not take that (d, M, form).
 bool group_order(int d, int M, int flags) {
-  return d >= 3 && !(flags & (GBS_MIXED | GBS_ALL_MINORS)) && group_supported(d, M, flags, false);
+  return d >= 3 && !(flags & GBS_ALL_MINORS) && group_supported(d, M, flags, false);
 }
 
 double item_cost(const WorkItem& w) {
@@ -467,7 +468,7 @@ gbs_status build_plan(BatchPlan* p, int n, const gbs_instance* inst, int K, int 
   for (int d = 3; d <= K; ++d) {
     p->n_gitems[d] = (uint32_t)gitems[d].size();
     if (gitems[d].empty()) continue;
-    p->g_lds[d] = group_batched_lds(d, p->g_max_M[d], &p->g_nwin[d]);
+    p->g_lds[d] = group_batched_lds(d, flags, p->g_max_M[d], &p->g_nwin[d]);
     e = group_batched_grid(d, flags, p->g_lds[d], ctx->cu_count, &p->g_grid[d]);
     if (e != hipSuccess) return to_status(e);
     if (t.group_wpc > 0) p->g_grid[d] = std::min(p->g_grid[d], ctx->cu_count * t.group_wpc);
@@ -493,6 +494,8 @@ gbs_status build_plan(BatchPlan* p, int n, const gbs_instance* inst, int K, int 
       g = GroupBatchInstance{};
       g.Qi = b.Qi;
       g.Qd = b.Qd;
+      g.pk = b.pk;
+      g.E = b.E;
       g.M = b.M;
       if (!grp[i]) continue;  // never referenced by an item
       for (int q = 1; q < d; ++q) {

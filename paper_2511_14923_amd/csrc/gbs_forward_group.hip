@@ -257,16 +257,15 @@ __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(1
 // a device work list with one atomic counter until the list is exhausted.  The
 // binomial table is filled once for the largest M (C(n, k) does not depend on
 // M); every workgroup leaves the loop when the counter passes the list's end.
-template <int D, int CONV, bool WANT_CUM>
+template <int D, int CONV, bool WANT_CUM, bool MIXED>
 __global__ __launch_bounds__(kGroupThreads) void forward_group_batched_kernel(
     const GroupBatchInstance* __restrict__ inst, const GroupBatchItem* __restrict__ items,
     uint32_t n_items, unsigned* __restrict__ counter, const uint64_t* __restrict__ binom,
     int max_M, DeviceStatus* __restrict__ st, int nwin_max) {
   constexpr bool DISP = false;
-  constexpr bool MIXED = false;
   constexpr int rmax = kGroupRmax;
   constexpr int NB = D - 1;
-  using GL = GroupLayout<NB, DISP>;
+  using GL = GroupLayout<NB, DISP, MIXED>;
   constexpr int NPm = GL::NPm;
   constexpr int NT = GL::NT;
   constexpr int NTS = GL::NTS;
@@ -298,10 +297,6 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_batched_kernel(
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const double* const mi = nullptr;
-  const double* const pk = nullptr;
-  const float* const E = nullptr;
-  const float* const Eodd = nullptr;
-  const uint32_t lde4 = 0;
 
   for (;;) {
     __syncthreads();  // every reader of the previous item index is done
@@ -318,8 +313,12 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_batched_kernel(
     double* __restrict__ m_out = I.m_out;
     double* __restrict__ k_out = I.k_out;
     double* __restrict__ p_out = I.p_out;
+    const double* __restrict__ pk = I.pk;
+    const float* __restrict__ E = I.E;
     const uint32_t ldq8 = 2u * (uint32_t)M * (uint32_t)sizeof(double);
-    const double* Qodd = Qi + 2 * (size_t)M;  // odd rows (p quadratures)
+    const double* Qodd = MIXED ? nullptr : Qi + 2 * (size_t)M;  // odd rows (p quadratures)
+    const uint32_t lde4 = 2u * (uint32_t)M * (uint32_t)sizeof(float);
+    const float* Eodd = MIXED ? E + 2 * (size_t)M : nullptr;
     const uint64_t desc = w.desc;
 #include "gbs_group_tile.inc"
   }
@@ -459,6 +458,14 @@ size_t group_lds_d(int d, int M) {
   }
 }
 
+int group_windows_d(int d, int M) {
+  switch (d) {
+    case 3: return group_windows<2, false>(M);
+    case 4: return group_windows<3, false>(M);
+    default: return group_windows<4, false>(M);
+  }
+}
+
 }  // namespace
 
 bool group_supported(int d, int M, int flags, bool displaced) {
@@ -563,27 +570,30 @@ void group_tiles(int d, int M, std::vector<uint64_t>* out) {
   out->insert(out->end(), t.begin(), t.end());
 }
 
-size_t group_batched_lds(int d, int max_M, int* nwin_max) {
-  switch (d) {
-    case 3: *nwin_max = group_windows<2, false>(max_M); return group_lds<2, false>(max_M);
-    case 4: *nwin_max = group_windows<3, false>(max_M); return group_lds<3, false>(max_M);
-    default: *nwin_max = group_windows<4, false>(max_M); return group_lds<4, false>(max_M);
-  }
+size_t group_batched_lds(int d, int flags, int max_M, int* nwin_max) {
+  *nwin_max = group_windows_d(d, max_M);
+  return (flags & GBS_MIXED) ? group_lds_d<false, true>(d, max_M) : group_lds_d<false>(d, max_M);
 }
 
 namespace {
 
-template <int D, int CONV>
+template <int D, int CONV, bool MIXED>
 const void* batched_fn() {
-  return reinterpret_cast<const void*>(&forward_group_batched_kernel<D, CONV, true>);
+  return reinterpret_cast<const void*>(&forward_group_batched_kernel<D, CONV, true, MIXED>);
+}
+
+template <int D>
+const void* batched_fn_f(int flags) {
+  if (flags & GBS_MIXED)
+    return (flags & GBS_PARITY) ? batched_fn<D, GBS_PARITY, true>() : batched_fn<D, GBS_CLICK, true>();
+  return (flags & GBS_PARITY) ? batched_fn<D, GBS_PARITY, false>() : batched_fn<D, GBS_CLICK, false>();
 }
 
 const void* pick_batched(int d, int flags) {
-  const bool parity = flags & GBS_PARITY;
   switch (d) {
-    case 3: return parity ? batched_fn<3, GBS_PARITY>() : batched_fn<3, GBS_CLICK>();
-    case 4: return parity ? batched_fn<4, GBS_PARITY>() : batched_fn<4, GBS_CLICK>();
-    default: return parity ? batched_fn<5, GBS_PARITY>() : batched_fn<5, GBS_CLICK>();
+    case 3: return batched_fn_f<3>(flags);
+    case 4: return batched_fn_f<4>(flags);
+    default: return batched_fn_f<5>(flags);
   }
 }
 
@@ -598,12 +608,12 @@ hipError_t group_batched_grid(int d, int flags, size_t lds, int cu_count, int* g
   return hipSuccess;
 }
 
-template <int D, int CONV>
+template <int D, int CONV, bool MIXED>
 static void launch_batched_t(const GroupBatchInstance* inst, const GroupBatchItem* items,
                              uint32_t n_items, unsigned* counter, int grid, int max_M,
                              int nwin_max, size_t lds, const uint64_t* binom, DeviceStatus* st,
                              hipStream_t s) {
-  hipLaunchKernelGGL((forward_group_batched_kernel<D, CONV, true>), dim3(grid),
+  hipLaunchKernelGGL((forward_group_batched_kernel<D, CONV, true, MIXED>), dim3(grid),
                      dim3(kGroupThreads), lds, s, inst, items, n_items, counter, binom, max_M, st,
                      nwin_max);
 }
@@ -613,8 +623,10 @@ using BatchedLaunch = void (*)(const GroupBatchInstance*, const GroupBatchItem*,
                                hipStream_t);
 
 template <int D>
-static BatchedLaunch pick_batched_launch(bool parity) {
-  return parity ? launch_batched_t<D, GBS_PARITY> : launch_batched_t<D, GBS_CLICK>;
+static BatchedLaunch pick_batched_launch(bool parity, bool mixed) {
+  if (mixed)
+    return parity ? launch_batched_t<D, GBS_PARITY, true> : launch_batched_t<D, GBS_CLICK, true>;
+  return parity ? launch_batched_t<D, GBS_PARITY, false> : launch_batched_t<D, GBS_CLICK, false>;
 }
 
 hipError_t launch_group_batched(int d, int flags, const GroupBatchInstance* inst,
@@ -622,12 +634,12 @@ hipError_t launch_group_batched(int d, int flags, const GroupBatchInstance* inst
                                 int grid, int max_M, int nwin_max, size_t lds,
                                 const uint64_t* binom, DeviceStatus* st, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  const bool parity = flags & GBS_PARITY;
+  const bool parity = flags & GBS_PARITY, mixed = flags & GBS_MIXED;
   BatchedLaunch fn;
   switch (d) {
-    case 3: fn = pick_batched_launch<3>(parity); break;
-    case 4: fn = pick_batched_launch<4>(parity); break;
-    case 5: fn = pick_batched_launch<5>(parity); break;
+    case 3: fn = pick_batched_launch<3>(parity, mixed); break;
+    case 4: fn = pick_batched_launch<4>(parity, mixed); break;
+    case 5: fn = pick_batched_launch<5>(parity, mixed); break;
     default: return hipErrorInvalidValue;
   }
   fn(inst, items, n_items, counter, grid, max_M, nwin_max, lds, binom, st, s);

@@ -62,9 +62,9 @@ __global__ __launch_bounds__(256) void forward_mixed_kernel(const double* __rest
   int s[D];
   colex_unrank<D>(r, M, bin, ld, s);
 
-  double mS, kS;
+  double mS, kS, pS;
   bool bad = false;
-  subset_mixed<D, CONV, WRITE_CUM>(pk, E, M, s, mS, kS, bad);
+  subset_mixed<D, CONV, WRITE_CUM>(pk, E, M, s, mS, kS, pS, bad);
   if (bad) latch_failure(st, D, (int64_t)r);
   if constexpr (WRITE_CORR) corr[r] = mS;
   if constexpr (WRITE_CUM) cum[r] = kS;

@@ -129,6 +129,8 @@ hipError_t launch_forward_group(int d, int M, int flags, const double* Qi, const
 struct GroupBatchInstance {
   const double* Qi;
   const double* Qd;
+  const double* pk;  // mixed form: single-mode vacuum probabilities
+  const float* E;    // mixed form: FP32 normalised couplings
   OrderTables tab;
   double* m_out;
   double* k_out;
@@ -143,8 +145,9 @@ struct GroupBatchItem {
 };
 // Tile descriptors of order d for M modes, appended to out (host).
 void group_tiles(int d, int M, std::vector<uint64_t>* out);
-// LDS bytes and bitmap windows of a batched launch of order d whose largest M is max_M.
-size_t group_batched_lds(int d, int max_M, int* nwin_max);
+// LDS bytes and bitmap windows of a batched launch of order d (FP64 or, with
+// GBS_MIXED, the mixed form) whose largest M is max_M.
+size_t group_batched_lds(int d, int flags, int max_M, int* nwin_max);
 // Workgroups that fit on the device at once for that LDS size (before capture).
 hipError_t group_batched_grid(int d, int flags, size_t lds, int cu_count, int* grid);
 hipError_t launch_group_batched(int d, int flags, const GroupBatchInstance* inst,

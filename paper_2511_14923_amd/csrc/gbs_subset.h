@@ -214,10 +214,11 @@ __device__ __forceinline__ void minors_mixed(const TriF<2 * (D - K)>& F, float r
 }
 
 // Mixed precision: FP32 deviation-form minors of the normalised Q, FP64 assembly.
+// pS is the full set's vacuum probability P_S (1 + rho_S).
 template <int D, int CONV, bool WANT_CUM>
 __device__ __forceinline__ void subset_mixed(const double* __restrict__ pk, const float* __restrict__ E,
                                              int M, const int (&s)[D], double& corr, double& cum,
-                                             bool& bad) {
+                                             double& pS, bool& bad) {
   constexpr int NS = 1 << D;
   double p1[D];
 #pragma unroll
@@ -257,6 +258,7 @@ __device__ __forceinline__ void subset_mixed(const double* __restrict__ pk, cons
     const int low = __builtin_ctz((unsigned)T);
     P[T] = P[T & (T - 1)] * p1[low];
   }
+  pS = fma(P[NS - 1], (double)rhoT[NS - 1], P[NS - 1]);
   double g[NS];
 #pragma unroll
   for (int T = 0; T < NS; ++T) {

@@ -40,28 +40,29 @@ def _alloc(batch, K, want_corr=True):
 
 
 def _singles(P, bufs, K, flags):
-    """Single-instance calls of the same arithmetic: the default kernels for
-    FP64 (the batched launch runs the group kernel at orders >= 3), the
-    all-minors kernel for the mixed form and for GBS_ALL_MINORS."""
-    if not (flags & (P.GBS_MIXED | P.GBS_ALL_MINORS)):
-        return [P.gbs_cumulants(M, s, K, flags) for (M, s, _, _) in bufs]
-    return [P.gbs_cumulants(M, s, K, flags | P.GBS_ALL_MINORS) for (M, s, _, _) in bufs]
+    """Single-instance calls of the same kernels: the default ones (the batched
+    launch runs the group kernel at orders >= 3, FP64 or mixed), the all-minors
+    kernel for GBS_ALL_MINORS."""
+    return [P.gbs_cumulants(M, s, K, flags) for (M, s, _, _) in bufs]
 
 
-def _agree(a, b, mixed=False):
-    """Same arithmetic compiled into two kernels: equal up to the last few ulps
-    of the terms that cancel (|terms| <= 2^K), or to the FP32 rounding of the
-    mixed form's deviations."""
+def _agree(a, b):
+    """Same FP64 arithmetic compiled into two kernels: equal up to the last few
+    ulps of the terms that cancel (|terms| <= 2^K)."""
     import torch
-    if mixed:
-        return bool(torch.allclose(a, b, rtol=1e-6, atol=1e-9))
     return bool(torch.allclose(a, b, rtol=1e-12, atol=1e-13))
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2, 16], ids=["fp64", "parity", "mixed", "all_minors"])
+@pytest.mark.parametrize("flags", [0, 1, 2, 16, 18],
+                         ids=["fp64", "parity", "mixed", "all_minors", "mixed_all_minors"])
 def test_batch48_equals_single_calls(P, flags):
     """The 48-instance M ~ U{40..144}, K = 4 workload: every instance's output
-    agrees with a separate gbs_cumulants call of the same kernel."""
+    agrees with a separate gbs_cumulants call.  FP64 runs the same arithmetic
+    on both sides; the mixed form's orders 1 and 2 take their FP32 roundings in
+    other orders in the two paths (all minors per subset against the
+    order-recursive kernels), so there the two differ, order by order and
+    normwise over all instances, by at most twice the mixed form's stated
+    bound (each side is within it of the exact value)."""
     import torch
     _say("case: batch48", flags)
     batch = G.make_batch()
@@ -71,10 +72,24 @@ def test_batch48_equals_single_calls(P, flags):
     singles = _singles(P, bufs, 4, flags)
     mixed = bool(flags & P.GBS_MIXED)
     worst = 0.0
+    num = {d: [0.0, 0.0] for d in range(1, 5)}
+    den = {d: [0.0, 0.0] for d in range(1, 5)}
     for (M, _, corr, cum), (c1, k1) in zip(bufs, singles):
         worst = max(worst, float((corr - c1).abs().max()), float((cum - k1).abs().max()))
-        assert _agree(corr, c1, mixed), M
-        assert _agree(cum, k1, mixed), M
+        if not mixed or flags & P.GBS_ALL_MINORS:
+            assert _agree(corr, c1), M
+            assert _agree(cum, k1), M
+            continue
+        for d in range(1, 5):
+            lo, hi = O.order_offset(M, d), O.order_offset(M, d + 1)
+            for j, (x, y) in enumerate(((corr, c1), (cum, k1))):
+                num[d][j] = max(num[d][j], float((x[lo:hi] - y[lo:hi]).abs().max()))
+                den[d][j] = max(den[d][j], float(y[lo:hi].abs().max()))
+    if mixed and not flags & P.GBS_ALL_MINORS:
+        for d in range(1, 5):
+            ec, ek = num[d][0] / den[d][0], num[d][1] / den[d][1]
+            _say(f"batched vs single mixed order {d}: corr {ec:.2e} cum {ek:.2e}")
+            assert ec <= 2 * MIXED_NORM_CORR[d] and ek <= 2 * MIXED_NORM_CUM[d], (d, ec, ek)
     _say("max |batched - single|", worst)
 
 
@@ -235,14 +250,15 @@ def test_order5_tables_scratch_and_fallback(P, c_oracle, conv):
             assert _agree(corr, c1), M
 
 
-def test_group_launches_in_timing(P):
-    """FP64 at K = 4: one all-minors launch (orders 1, 2) and one group launch
-    per order 3, 4 appear as 'batched' stages."""
+@pytest.mark.parametrize("flags", [0, 2], ids=["fp64", "mixed"])
+def test_group_launches_in_timing(P, flags):
+    """K = 4, FP64 or mixed: one all-minors launch (orders 1, 2) and one group
+    launch per order 3, 4 appear as 'batched' stages."""
     import torch
-    _say("case: batched group timing")
+    _say("case: batched group timing", flags)
     batch = G.make_batch(count=4, seed=19, m_range=(12, 40))
     bufs = _alloc(batch, 4)
-    P.gbs_cumulants_batched(bufs, 4, P.GBS_TIMING)
+    P.gbs_cumulants_batched(bufs, 4, P.GBS_TIMING | flags)
     torch.cuda.synchronize()
     orders = sorted(o for st, o, _ in P.gbs_last_timings() if st == "batched")
     assert orders == [0, 3, 4], orders
