@@ -36,8 +36,7 @@ __device__ __forceinline__ void latch_failure(DeviceStatus* st, int order, int64
   }
 }
 
-// 1/sqrt(x) in FP64: hardware estimate refined by two Newton steps
-// y <- y + y (1 - x y^2) / 2, each step squaring the relative error.
+// 1/sqrt(x) in FP64: the hardware estimate refined by one Halley step.
 __device__ __forceinline__ double rsqrt_f64(double x) {
   // The instruction's estimate y is good to about 2^-25 relative; one step of
   // Halley's iteration for x y^2 = 1, y <- y (1 + e/2 + 3e^2/8) with
