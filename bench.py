@@ -206,8 +206,8 @@ def batched_and_adjoint(P, torch, G, steps):
             "frac_of_fp64_peak": flops / (kms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS,
             "tuned_shape": tuned, "autotune_seconds": t_tune,
             "kernel": ("persistent work lists: orders 1-2 all-minors, orders 3-4 the group "
-                       "kernel, one launch per order" if fl == 0 else
-                       "persistent work list: every order all-minors (normalised FP32 minors)")}
+                       "kernel, one launch per order" + ("" if fl == 0 else
+                       " (FP32 deviations of the normalised Q, FP64 probabilities and sums)"))}
         log(f"[bench] {label}: {1e3 * wall:.2f} ms per call, kernels {kms:.2f} ms, tuned {tuned}")
     del bufs
     inst = G.make_instance("grad_m144_k3")
