@@ -99,11 +99,10 @@ struct GroupLayout {
   static constexpr int nLe = 7;
   static constexpr int nL = nLb + nLe;
   static constexpr int dP = MIXED ? (nL + 1) / 2 : nL;  // p(B'), p(B) (displaced: with exp(-|z|^2 / 2))
-  static constexpr int dMB = dP + 2;            // m(B)
-  static constexpr int dMW = dMB + 1;           // m(W), W = 1 .. FULLP (index W - 1)
-  static constexpr int dKB = dMW + (NP - 1);    // k(R + e), R = 0 .. FULLP
-  static constexpr int dME = dKB + NP;          // m(R + e), R = 0 .. FULLP
-  static constexpr int dZ = dME + NP;           // displaced: z_{b_0} [2], z_e(B) [2]
+  // coefficients c_B(V), V subset of B, of k(S) = sum_V c_B(V) p({a} + V); 16-byte aligned pairs
+  static constexpr int dC = (dP + 2 + 1) & ~1;
+  static constexpr int dMB = dC + NU;           // m(B)
+  static constexpr int dZ = dMB + 1;            // displaced: z_{b_0} [2], z_e(B) [2]
   static constexpr int nD = dZ + (DISP ? 4 : 0);
   static constexpr int nDpad = (nD + 1) & ~1;
   // per-B record, 32-bit words
@@ -124,14 +123,11 @@ struct GroupLayout {
   static constexpr int uY = 0;                  // y_P [k < 2|P|][2]
   static constexpr int uT = MIXED ? I0 / 2 : I0;        // t_e [r][2]
   static constexpr int uS = uT + (MIXED ? 1 : 2);       // Schur complement of Q_P in Q_{P + a}: s00, s10, s11
-  static constexpr int uPK = uS + (MIXED ? 1 : 2);      // mixed: p_a = det(Q_aa)^(-1/2) (FP64)
-  static constexpr int uPT = uPK + (MIXED ? 1 : 0);     // nu, nue of the W subset of P (FP64)
-  // mixed (whose records leave LDS room): the cumulants k({a} + W + e), W
-  // subset of P, of the recursion's b_0-free half, one FP64 each
-  static constexpr bool KLO = MIXED;
-  static constexpr int NPS = NTS / 2;                   // subsets of P
-  static constexpr int uKL = uPT + (NTS + 1) / 2;
-  static constexpr int rUnits = uKL + (KLO ? (NPS + 1) / 2 : 0);
+  // FP64: s11 and nu_T share the second unit of uS; mixed: p_a = det(Q_aa)^(-1/2)
+  // and nu_T (FP64) share uPK.  nu_T = sum_{U subset T} s(U) p({a} + U).
+  static constexpr int uPK = uS + (MIXED ? 1 : 2);
+  static constexpr int uPT = uPK + (MIXED ? 1 : 0);     // p({a} + U), U subset of T (FP64)
+  static constexpr int rUnits = uPT + NTS / 2;
   static constexpr int rbytes = rUnits * 16;    // per record
   // per-group record (Cholesky of Q_T in the order P, e), doubles
   static constexpr int gP = 0;                  // L_P: tri(i, j), 1/L_ii on the diagonal
@@ -234,7 +230,6 @@ __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(1
   __shared__ uint32_t s_ntile, s_r0, s_ngroups, s_nrec;
   __shared__ uint32_t s_gbase[kGroupG];      // first (T, a) record of each group
   __shared__ int s_gT[kGroupG][NB - 1];       // modes of T, in the order P, e
-  __shared__ int s_gc[kGroupG];               // record slot of a non-empty B of each group
 
   for (int i = threadIdx.x; i < (D + 1) * ld; i += blockDim.x) {
     const int kk = i / ld, nn = i - kk * ld;
@@ -287,7 +282,6 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_batched_kernel(
   __shared__ uint32_t s_ntile, s_r0, s_ngroups, s_nrec;
   __shared__ uint32_t s_gbase[kGroupG];
   __shared__ int s_gT[kGroupG][NB - 1];
-  __shared__ int s_gc[kGroupG];
   __shared__ uint32_t s_item;
 
   for (int i = threadIdx.x; i < (D + 1) * ld; i += blockDim.x) {
