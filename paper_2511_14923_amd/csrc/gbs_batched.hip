@@ -402,7 +402,7 @@ gbs_status build_plan(BatchPlan* p, int n, const gbs_instance* inst, int K, int 
     for (int i : by_M) {
       if (!group_order(d, inst[i].M, flags)) continue;
       tiles.clear();
-      group_tiles(d, inst[i].M, &tiles);
+      group_tiles(d, inst[i].M, (flags & GBS_MIXED) != 0, &tiles);
       for (uint64_t desc : tiles) gitems[d].push_back(GroupBatchItem{(uint32_t)i, 0u, desc});
       p->g_max_M[d] = std::max(p->g_max_M[d], inst[i].M);
       grp[i] = true;

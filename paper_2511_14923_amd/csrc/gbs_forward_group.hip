@@ -51,8 +51,10 @@ namespace gbs {
 
 namespace {
 
-constexpr int kGroupB = 40;         // B's per tile at most
-constexpr int kGroupG = 16;         // groups per tile at most
+// B's and groups per tile at most (per precision: GroupLayout::kB, kG) bound
+// these; the walk and descriptor limits below cover every layout
+constexpr int kGroupBMax = 64;
+constexpr int kGroupGMax = 16;
 constexpr int kGroupThreads = 256;  // threads per workgroup (4 waves)
 constexpr int kGroupRmax = 148;     // (T, a) records per tile at most (M - d + 1 needed)
 // Workgroups per CU in one single-instance launch; beyond that a workgroup takes
@@ -69,17 +71,22 @@ constexpr int kDescNbBits = 7;
 constexpr int kDescTShift = kDescNbShift + kDescNbBits;
 constexpr uint64_t kDescBetaMask = (1ull << kDescNbShift) - 1;
 constexpr uint64_t kDescNbMask = (1ull << kDescNbBits) - 1;
-static_assert(kGroupB <= (int)kDescNbMask, "the B count of a tile must fit its descriptor field");
+static_assert(kGroupBMax <= (int)kDescNbMask, "the B count of a tile must fit its descriptor field");
 static_assert(kDescTShift + 3 * 8 <= 64, "the descriptor holds three 8-bit modes");
-// steps of a lane's walk at most: the groups of a tile (kGroupG) and the empty
+// steps of a lane's walk at most: the groups of a tile (kGroupGMax) and the empty
 // T (min T = 0) between them, at most two per group
-constexpr int kWalkMax = 3 * kGroupG + 4;
+constexpr int kWalkMax = 3 * kGroupGMax + 4;
 
 template <int NB, bool DISP, bool MIXED = false>
 struct GroupLayout {
-  // B's per tile: fewer for displaced states, whose larger records must still
-  // let three workgroups share a compute unit's LDS
-  static constexpr int kB = DISP ? 36 : kGroupB;
+  // B's and groups per tile: as many as let three workgroups share a compute
+  // unit's 160 KB of LDS at M = 144 (order 5 at M = 144: FP64 40 -> 52 B's
+  // 5.57 -> 5.27 ms; mixed 40 -> 64 B's 5.22 -> 4.70 ms); the smaller FP32
+  // factor rows and records of the mixed form leave room for a full wavefront
+  // of B's.  kG is a power of two (the record builder's binary search).
+  static constexpr int kB = DISP ? 48 : (MIXED ? 64 : 52);
+  static constexpr int kG = MIXED ? 16 : 8;
+  static_assert(kB <= kGroupBMax && kG <= kGroupGMax && (kG & (kG - 1)) == 0, "tile shape");
   static constexpr int NPm = NB - 2;       // |P|
   static constexpr int NT = NB - 1;        // |T|
   static constexpr int NTS = 1 << NT;      // subsets of T
@@ -223,13 +230,13 @@ __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(1
   unsigned char* brec = smem;
   unsigned char* rrec = smem + GL::kB * GL::bytes;
   double* grec = reinterpret_cast<double*>(rrec + (size_t)rmax * GL::rbytes);
-  uint32_t* bin = reinterpret_cast<uint32_t*>(grec + kGroupG * GL::gN);
+  uint32_t* bin = reinterpret_cast<uint32_t*>(grec + GL::kG * GL::gN);
   const int ld = M + 1;
   uint64_t* bits = reinterpret_cast<uint64_t*>(bin + (((D + 1) * ld + 1) & ~1));
   unsigned char* first = reinterpret_cast<unsigned char*>(bits + nwin_max);
   __shared__ uint32_t s_ntile, s_r0, s_ngroups, s_nrec;
-  __shared__ uint32_t s_gbase[kGroupG];      // first (T, a) record of each group
-  __shared__ int s_gT[kGroupG][NB - 1];       // modes of T, in the order P, e
+  __shared__ uint32_t s_gbase[GL::kG];      // first (T, a) record of each group
+  __shared__ int s_gT[GL::kG][NB - 1];       // modes of T, in the order P, e
 
   for (int i = threadIdx.x; i < (D + 1) * ld; i += blockDim.x) {
     const int kk = i / ld, nn = i - kk * ld;
@@ -275,13 +282,13 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_batched_kernel(
   unsigned char* brec = smem;
   unsigned char* rrec = smem + GL::kB * GL::bytes;
   double* grec = reinterpret_cast<double*>(rrec + (size_t)rmax * GL::rbytes);
-  uint32_t* bin = reinterpret_cast<uint32_t*>(grec + kGroupG * GL::gN);
+  uint32_t* bin = reinterpret_cast<uint32_t*>(grec + GL::kG * GL::gN);
   const int ld = max_M + 1;
   uint64_t* bits = reinterpret_cast<uint64_t*>(bin + (((D + 1) * ld + 1) & ~1));
   unsigned char* first = reinterpret_cast<unsigned char*>(bits + nwin_max);
   __shared__ uint32_t s_ntile, s_r0, s_ngroups, s_nrec;
-  __shared__ uint32_t s_gbase[kGroupG];
-  __shared__ int s_gT[kGroupG][NB - 1];
+  __shared__ uint32_t s_gbase[GL::kG];
+  __shared__ int s_gT[GL::kG][NB - 1];
   __shared__ uint32_t s_item;
 
   for (int i = threadIdx.x; i < (D + 1) * ld; i += blockDim.x) {
@@ -324,10 +331,10 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_batched_kernel(
 namespace {
 
 // Tiles of consecutive B's (colex order of the (d-1)-subsets) such that each
-// holds at most kB B's of at most kGroupG groups, which need at most rmax
+// holds at most kB B's of at most kG groups, which need at most rmax
 // (T, a) records.  A group is all B = {b_0} + T with b_0 < min T; within a tile
 // it needs the records a < (largest b_0 of the group in the tile).
-std::vector<uint64_t> plan_tiles(int M, int NB, int rmax, int kB) {
+std::vector<uint64_t> plan_tiles(int M, int NB, int rmax, int kB, int kG) {
   std::vector<uint64_t> tiles;
   uint32_t beta = 0, tstart = 0;
   uint64_t tfirst = 0;  // modes of the T of the tile's first B, 8 bits each
@@ -350,7 +357,7 @@ std::vector<uint64_t> plan_tiles(int M, int NB, int rmax, int kB) {
     while (k < gsize) {
       int n = std::min(gsize - k, kB - nB);
       int need = k + n - 1;  // records a < max b_0 = k + n - 1
-      if (rec + need > rmax || ng == kGroupG) {
+      if (rec + need > rmax || ng == kG) {
         close();
         n = std::min(gsize - k, kB);
         need = k + n - 1;
@@ -379,9 +386,9 @@ std::vector<uint64_t> plan_tiles(int M, int NB, int rmax, int kB) {
 }
 
 struct PlanKey {
-  int device, M, NB, kB;
+  int device, M, NB, kB, kG;
   bool operator<(const PlanKey& o) const {
-    return std::tie(device, M, NB, kB) < std::tie(o.device, o.M, o.NB, o.kB);
+    return std::tie(device, M, NB, kB, kG) < std::tie(o.device, o.M, o.NB, o.kB, o.kG);
   }
 };
 struct Plan {
@@ -394,17 +401,17 @@ std::map<PlanKey, Plan> g_plans;
 
 int group_rmax(int M, int NB) { return M - NB <= kGroupRmax ? M - NB : -1; }
 
-hipError_t get_plan(int M, int NB, int kB, Plan* out) {
+hipError_t get_plan(int M, int NB, int kB, int kG, Plan* out) {
   int device = 0;
   hipError_t e = hipGetDevice(&device);
   if (e != hipSuccess) return e;
   std::lock_guard<std::mutex> lock(g_plan_mu);
-  auto it = g_plans.find(PlanKey{device, M, NB, kB});
+  auto it = g_plans.find(PlanKey{device, M, NB, kB, kG});
   if (it != g_plans.end()) {
     *out = it->second;
     return hipSuccess;
   }
-  const std::vector<uint64_t> tiles = plan_tiles(M, NB, group_rmax(M, NB), kB);
+  const std::vector<uint64_t> tiles = plan_tiles(M, NB, group_rmax(M, NB), kB, kG);
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
@@ -420,7 +427,7 @@ hipError_t get_plan(int M, int NB, int kB, Plan* out) {
       return e;
     }
   }
-  g_plans[PlanKey{device, M, NB, kB}] = p;
+  g_plans[PlanKey{device, M, NB, kB, kG}] = p;
   *out = p;
   return hipSuccess;
 }
@@ -428,9 +435,9 @@ hipError_t get_plan(int M, int NB, int kB, Plan* out) {
 std::mutex g_host_plan_mu;
 std::map<PlanKey, std::vector<uint64_t>> g_host_plans;
 
-template <int NB, bool DISP>
+template <int NB, bool DISP, bool MIXED = false>
 int group_windows(int M) {
-  return (GroupLayout<NB, DISP>::kB * (M - NB) + 63) / 64 + 1;
+  return (GroupLayout<NB, DISP, MIXED>::kB * (M - NB) + 63) / 64 + 1;
 }
 
 template <int NB, bool DISP, bool MIXED = false>
@@ -438,9 +445,9 @@ size_t group_lds(int M) {
   using GL = GroupLayout<NB, DISP, MIXED>;
   const int D = NB + 1;
   return (size_t)GL::kB * GL::bytes + (size_t)kGroupRmax * GL::rbytes +
-         (size_t)kGroupG * GL::gbytes +
+         (size_t)GL::kG * GL::gbytes +
          (size_t)(((D + 1) * (M + 1) + 1) & ~1) * sizeof(uint32_t) +
-         (size_t)group_windows<NB, DISP>(M) * (sizeof(uint64_t) + 1);
+         (size_t)group_windows<NB, DISP, MIXED>(M) * (sizeof(uint64_t) + 1);
 }
 
 template <bool DISP, bool MIXED = false>
@@ -452,13 +459,18 @@ size_t group_lds_d(int d, int M) {
   }
 }
 
+template <bool MIXED>
 int group_windows_d(int d, int M) {
   switch (d) {
-    case 3: return group_windows<2, false>(M);
-    case 4: return group_windows<3, false>(M);
-    default: return group_windows<4, false>(M);
+    case 3: return group_windows<2, false, MIXED>(M);
+    case 4: return group_windows<3, false, MIXED>(M);
+    default: return group_windows<4, false, MIXED>(M);
   }
 }
+
+// Tile shape of the zero-mean plans (the same for every order).
+int plan_kb(bool mixed) { return mixed ? GroupLayout<2, false, true>::kB : GroupLayout<2, false>::kB; }
+int plan_kg(bool mixed) { return mixed ? GroupLayout<2, false, true>::kG : GroupLayout<2, false>::kG; }
 
 }  // namespace
 
@@ -473,13 +485,14 @@ bool group_supported(int d, int M, int flags, bool displaced) {
   return lds <= 64 * 1024;
 }
 
-const std::vector<uint64_t>& group_plan_host(int d, int M) {
+const std::vector<uint64_t>& group_plan_host(int d, int M, bool mixed) {
   const int NB = d - 1;
-  const int kB = GroupLayout<2, false>::kB;  // the zero-mean tile width (same for every order)
+  const int kB = plan_kb(mixed), kG = plan_kg(mixed);
   std::lock_guard<std::mutex> lock(g_host_plan_mu);
-  auto it = g_host_plans.find(PlanKey{-1, M, NB, kB});
+  const PlanKey key{-1, M, NB, kB, kG};
+  auto it = g_host_plans.find(key);
   if (it == g_host_plans.end())
-    it = g_host_plans.emplace(PlanKey{-1, M, NB, kB}, plan_tiles(M, NB, group_rmax(M, NB), kB)).first;
+    it = g_host_plans.emplace(key, plan_tiles(M, NB, group_rmax(M, NB), kB, kG)).first;
   return it->second;  // map nodes are never erased: the reference stays valid
 }
 
@@ -509,11 +522,12 @@ static hipError_t launch_group_t(int M, const GroupArgs& g, const uint64_t* bino
     plan.ntiles = ext->ntiles;
     plan.grid = ext->grid;
   } else {
-    hipError_t e = get_plan(M, NB, GroupLayout<NB, DISP>::kB, &plan);
+    using GL = GroupLayout<NB, DISP, MIXED>;
+    hipError_t e = get_plan(M, NB, GL::kB, GL::kG, &plan);
     if (e != hipSuccess) return e;
   }
   if (plan.ntiles == 0) return hipSuccess;
-  const int nwin = group_windows<NB, DISP>(M);
+  const int nwin = group_windows<NB, DISP, MIXED>(M);
   const size_t lds = group_lds<NB, DISP, MIXED>(M);
   hipLaunchKernelGGL((forward_group_kernel<D, CONV, WC, DISP, MIXED>), dim3(plan.grid),
                      dim3(kGroupThreads), lds, s, g.Qi, g.Qd, g.mi, g.pk, g.E, M, plan.dev,
@@ -557,15 +571,14 @@ static hipError_t launch_group_c(int M, int flags, const GroupArgs& g, const uin
   return launch_group_v<D, GBS_CLICK>(M, flags, g, binom, tab, m_out, k_out, p_out, st, s, ext);
 }
 
-void group_tiles(int d, int M, std::vector<uint64_t>* out) {
+void group_tiles(int d, int M, bool mixed, std::vector<uint64_t>* out) {
   const int NB = d - 1;
-  const int kB = GroupLayout<2, false>::kB;  // the zero-mean tile width (same for every order)
-  const std::vector<uint64_t> t = plan_tiles(M, NB, group_rmax(M, NB), kB);
+  const std::vector<uint64_t> t = plan_tiles(M, NB, group_rmax(M, NB), plan_kb(mixed), plan_kg(mixed));
   out->insert(out->end(), t.begin(), t.end());
 }
 
 size_t group_batched_lds(int d, int flags, int max_M, int* nwin_max) {
-  *nwin_max = group_windows_d(d, max_M);
+  *nwin_max = (flags & GBS_MIXED) ? group_windows_d<true>(d, max_M) : group_windows_d<false>(d, max_M);
   return (flags & GBS_MIXED) ? group_lds_d<false, true>(d, max_M) : group_lds_d<false>(d, max_M);
 }
 

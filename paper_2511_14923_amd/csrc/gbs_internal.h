@@ -114,7 +114,7 @@ struct GroupPlanRef {
 // Host copy of the zero-mean tile plan of order d for M modes (built once,
 // kept until the process ends) and the grid a single-instance launch uses
 // on a device with cu_count compute units.
-const std::vector<uint64_t>& group_plan_host(int d, int M);
+const std::vector<uint64_t>& group_plan_host(int d, int M, bool mixed);
 uint32_t group_plan_grid(uint32_t ntiles, int cu_count);
 hipError_t launch_forward_group(int d, int M, int flags, const double* Qi, const double* Qd,
                                 const double* mi, const double* pk, const float* E,
@@ -144,7 +144,7 @@ struct GroupBatchItem {
   uint64_t desc;  // tile descriptor of the instance's plan
 };
 // Tile descriptors of order d for M modes, appended to out (host).
-void group_tiles(int d, int M, std::vector<uint64_t>* out);
+void group_tiles(int d, int M, bool mixed, std::vector<uint64_t>* out);
 // LDS bytes and bitmap windows of a batched launch of order d (FP64 or, with
 // GBS_MIXED, the mixed form) whose largest M is max_M.
 size_t group_batched_lds(int d, int flags, int max_M, int* nwin_max);

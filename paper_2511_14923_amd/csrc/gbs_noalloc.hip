@@ -86,7 +86,7 @@ NoAllocLayout layout(int M, int K, int flags, bool corr_given) {
   L.st = off; off += align256(sizeof(DeviceStatus));
   for (int d = 3; d <= K && rec; ++d) {
     if (!group_supported(d, M, flags, false)) continue;
-    const std::vector<uint64_t>& t = group_plan_host(d, M);
+    const std::vector<uint64_t>& t = group_plan_host(d, M, mixed);
     L.ntiles[d] = (uint32_t)t.size();
     L.plan[d] = off;
     off += align256(t.size() * sizeof(uint64_t));
@@ -152,7 +152,7 @@ extern "C" GBS_API gbs_status gbs_cumulants_noalloc(int32_t M, const double* sig
     if (any_plan && D->plan_key != key) {
       for (int d = 3; d <= max_order && e == hipSuccess; ++d) {
         if (!L.ntiles[d]) continue;
-        const std::vector<uint64_t>& t = group_plan_host(d, M);
+        const std::vector<uint64_t>& t = group_plan_host(d, M, (flags & GBS_MIXED) != 0);
         e = hipMemcpyAsync(b + L.plan[d], t.data(), t.size() * sizeof(uint64_t),
                            hipMemcpyHostToDevice, s);
       }

@@ -1,11 +1,12 @@
 // Host check of the group kernel's tile plans and descriptors (built and run
 // by tests/test_group_plan.py; no GPU needed).  For every (M, order) the group
 // kernel takes, the plan must cover every subset exactly once, and each tile's
-// descriptor must decode to its first B, its B count (1 .. kGroupB) and the T
+// descriptor must decode to its first B, its B count (1 .. kB) and the T
 // of that B, with every lane's walk over the groups (the kernel's way of
 // finding its B) landing on the B that colex unranking gives, within the
 // walk's step limit; each tile's groups and (T, a) records must fit the
-// kernel's LDS bounds.
+// kernel's LDS bounds.  Both tile shapes are checked: the FP64 one and the
+// wider one of the mixed form.
 #include <cstdio>
 
 #include "gbs_forward_group.hip"
@@ -37,11 +38,13 @@ int main() {
   long fails = 0, tiles_total = 0, lanes = 0;
   int max_walk = 0;
   const int Ms[] = {3, 4, 5, 6, 12, 13, 16, 17, 40, 64, 100, 143, 144, 145, 150, 152};
+  for (int mixed = 0; mixed < 2; ++mixed)
   for (int M : Ms) {
     for (int d = 3; d <= 5; ++d) {
-      if (d > M || !group_supported(d, M, 0, false)) continue;
+      if (d > M || !group_supported(d, M, mixed ? GBS_MIXED : 0, false)) continue;
       const int NB = d - 1, nt = NB - 1;
-      const std::vector<uint64_t>& tiles = group_plan_host(d, M);
+      const int kB = plan_kb(mixed != 0), kG = plan_kg(mixed != 0);
+      const std::vector<uint64_t>& tiles = group_plan_host(d, M, mixed != 0);
       uint64_t beta = 0, subsets = 0;
       for (uint64_t desc : tiles) {
         ++tiles_total;
@@ -49,7 +52,7 @@ int main() {
         const int nB = (int)((desc >> kDescNbShift) & kDescNbMask);
         int t0[3] = {0, 0, 0};
         for (int j = 0; j < nt; ++j) t0[j] = (int)((desc >> (kDescTShift + 8 * j)) & 255);
-        if (beta0 != beta || nB < 1 || nB > kGroupB) {
+        if (beta0 != beta || nB < 1 || nB > kB) {
           if (fails++ < 10) printf("M=%d d=%d tile at %u: beta0 %u, nB %d\n", M, d, (unsigned)beta, beta0, nB);
         }
         uint32_t tpart = 0;
@@ -83,7 +86,7 @@ int main() {
           ++lanes;
         }
         records += group_max_b0;
-        if ((groups > kGroupG || records > M - NB) && fails++ < 10)
+        if ((groups > kG || records > M - NB) && fails++ < 10)
           printf("M=%d d=%d tile at %u: %d groups, %d records\n", M, d, beta0, groups, records);
         beta += (uint64_t)nB;
       }
