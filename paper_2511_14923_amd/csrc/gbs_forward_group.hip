@@ -46,6 +46,7 @@
 #include <vector>
 
 #include "gbs_internal.h"
+#include "gbs_subset.h"
 
 namespace gbs {
 

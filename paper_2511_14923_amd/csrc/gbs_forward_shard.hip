@@ -9,20 +9,19 @@
 //     Q_B (each block in turn is eliminated -- Schur complement -- or dropped);
 //     every node keeps its pivot's inverse P^{-1} and u = P^{-1} A_{P,rest},
 //     every leaf U gives p(U); then m(W) for every W subset of B (subset zeta
-//     transform) and k(R + e) for every R subset of B' = B \ {e} (fixed-element
-//     recursion on e);
+//     transform) and the coefficients c_B(V) of the cumulant as a linear form in
+//     the p({a} + V) (cumulant_coefficients, gbs_subset.h);
 //   phase 2, one lane per subset: the same recursion carried on a's block.  With
 //     C the coupling of the remaining B blocks to a and S_a a's 2x2 block (both
 //     reduced by the eliminated blocks), eliminating block b gives
 //       S_a' = S_a - C_b^T P^{-1} C_b,    C_rest' = C_rest - u^T C_b,
 //     dropping it leaves both unchanged, and at the leaf U
 //       det(Q_{U+a}) = det(Q_U) det(S_a),  so  p({a} + U) = p(U) det(S_a)^(-1/2)
-//     (block elimination of the bordered matrix).  Then m({a} + W) = m(W) - nu(W)
-//     with nu the subset zeta transform of the signed p({a} + U) (parity:
-//     -c(W) + 2 (-1)^|W| nu(W); Eq. corre_cov_main split by whether the subset
-//     contains a), and the cumulant by the fixed-element recursion on e (Eq.
-//     cumulant_corr_main grouped by the block that contains e; App. B, Eq.
-//     correlators_expanded_2) with the B-only k(R + e) from phase 1.
+//     (block elimination of the bordered matrix).  Then m(S) = m(B) - nu(B)
+//     with nu(B) = sum_V s(V) p({a} + V) (parity: -m(B) + 2 (-1)^|B| nu(B);
+//     Eq. corre_cov_main split by whether the subset contains a), and
+//     k(S) = sum_V c_B(V) p({a} + V) (Eq. cumulant_corr_main with the block
+//     that contains a singled out).
 // A subset thus costs 2^(d-1) 2x2 determinants and the a-block updates, where
 // the all-minors kernel pays all 2^d - 1 minors of Q_S; its reads of Q are the
 // a columns of B's rows (consecutive a across a wavefront) and a's diagonal
@@ -57,9 +56,9 @@ __host__ __device__ constexpr int node_offset(int k, unsigned mask) {
 template <int NB>
 struct ShardRec {
   static constexpr int oP = node_offset<NB>(NB, 0u);  // p(U), U subset of B (bit i <-> b_i)
-  static constexpr int oM = oP + (1 << NB);           // m(W), W subset of B
-  static constexpr int oK = oM + (1 << NB);           // k(R + e), R subset of B'
-  static constexpr int n = oK + (1 << (NB - 1));
+  static constexpr int oC = oP + (1 << NB);           // c_B(V), V subset of B
+  static constexpr int oMB = oC + (1 << NB);          // m(B)
+  static constexpr int n = oMB + 1;
   static constexpr int stride = (n + 1) & ~1;
 };
 
@@ -161,9 +160,6 @@ void forward_shard_kernel(
   constexpr int NB = D - 1;
   constexpr int NU = 1 << NB;               // subsets of B
   constexpr int FULL = NU - 1;
-  constexpr int NX = 1 << (D - 1);           // subsets of X = {a} + B'
-  constexpr int FULLX = NX - 1;
-  constexpr int EBIT = 1 << (NB - 1);        // e as a B bit
   using R = ShardRec<NB>;
   __shared__ double s_rec[kShardB * R::stride];
   __shared__ int s_b[kShardB][NB];
@@ -208,21 +204,13 @@ void forward_shard_kernel(
           double m[NU];
           correlators_from_vacuum<NB, CONV>(p, m);
 #pragma unroll
-          for (int u = 0; u < NU; ++u) {
-            rec[R::oP + u] = p[u];
-            rec[R::oM + u] = m[u];
-          }
-          // k(R + e) = m(R + e) - sum_{R' proper subset of R} k(R' + e) m(R \ R')
-          constexpr int NR = 1 << (NB - 1);
-          double k[NR];
+          for (int u = 0; u < NU; ++u) rec[R::oP + u] = p[u];
+          rec[R::oMB] = m[FULL];
+          if constexpr (WK) {
+            double cq[NU];
+            cumulant_coefficients<NB, CONV>(m, cq);
 #pragma unroll
-          for (int Rs = 0; Rs < NR; ++Rs) {
-            double v = m[Rs | EBIT];
-#pragma unroll
-            for (int Rp = 0; Rp < Rs; ++Rp)
-              if ((Rp & Rs) == Rp) v = fma(-k[Rp], m[Rs ^ Rp], v);
-            k[Rs] = v;
-            rec[R::oK + Rs] = v;
+            for (int v = 0; v < NU; ++v) rec[R::oC + v] = cq[v];
           }
         }
       }
@@ -269,47 +257,18 @@ void forward_shard_kernel(
       a_tree<NB, 0, 0u>(rec, C, qa0.x, qa0.y, qa11, pa, bad);
       if (bad) latch_failure(st, D, (int64_t)(rank0 + out));
 
-      // nu(W) by the subset zeta transform of the signed p({a} + U), then m({a} + W)
-      double nu[NU];
+      // m(S) = m(B) - nu(B) (click) or -m(B) + 2 (-1)^|B| nu(B) (parity)
+      double nuB = 0.0;
 #pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const int t = popcount_c((unsigned)u);
-        if (CONV == GBS_CLICK) nu[u] = (t & 1) ? -pa[u] : pa[u];
-        else nu[u] = ((t & 1) ? -1.0 : 1.0) * (double)(1 << t) * pa[u];
+      for (int u = 0; u < NU; ++u) nuB = fma(vacuum_sign<CONV>(u), pa[u], nuB);
+      if constexpr (WC) {
+        const double mB = rec[R::oMB];
+        corr[out] = (CONV == GBS_CLICK) ? mB - nuB : fma((NB & 1) ? -2.0 : 2.0, nuB, -mB);
       }
-#pragma unroll
-      for (int bit = 0; bit < NB; ++bit)
-#pragma unroll
-        for (int u = 0; u < NU; ++u)
-          if (u & (1 << bit)) nu[u] += nu[u ^ (1 << bit)];
-      double ma[NU];
-#pragma unroll
-      for (int w = 0; w < NU; ++w) {
-        const double mw = rec[R::oM + w];
-        if (CONV == GBS_CLICK) ma[w] = mw - nu[w];
-        else ma[w] = fma((popcount_c((unsigned)w) & 1) ? -2.0 : 2.0, nu[w], -mw);
-      }
-      if constexpr (WC) corr[out] = ma[FULL];
       if constexpr (WK) {
-        // K(Y) = k(Y + e) for Y subset of X (bit 0 <-> a, bit i <-> b_{i-1}):
-        // the ones without a from phase 1, the ones with a by the recursion
-        double Kv[NX];
-#pragma unroll
-        for (int Y = 0; Y < NX; Y += 2) Kv[Y] = rec[R::oK + (Y >> 1)];
-        auto mu_of = [&](int Y) -> double {  // m(Y), Y subset of X
-          return (Y & 1) ? ma[Y >> 1] : rec[R::oM + (Y >> 1)];
-        };
         double kS = 0.0;
 #pragma unroll
-        for (int Y = 1; Y < NX; Y += 2) {
-          const int W = (Y >> 1) | EBIT;  // Y + e as a subset of {a} + B, less a
-          double v = ma[W];
-#pragma unroll
-          for (int Rr = 0; Rr < Y; ++Rr)
-            if ((Rr & Y) == Rr) v = fma(-Kv[Rr], mu_of(Y ^ Rr), v);
-          Kv[Y] = v;
-          if (Y == FULLX) kS = v;
-        }
+        for (int u = 0; u < NU; ++u) kS = fma(rec[R::oC + u], pa[u], kS);
         cum[out] = kS;
       }
     }

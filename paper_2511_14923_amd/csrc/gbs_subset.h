@@ -121,6 +121,63 @@ __device__ __forceinline__ double cumulant_from_correlators(const double (&m)[1 
   return k[NR - 1];
 }
 
+// Coefficients c(V), V subset of B (NB modes, bit i <-> b_i), of the cumulant of
+// {a} + B as a linear form in the vacuum probabilities p({a} + V):
+//   k({a} + B) = sum_V c(V) p({a} + V),
+// from the B-only correlators m (m[0] = 1).  Eq. cumulant_corr_main with the
+// block that contains a singled out reads k({a} + B) = sum_U m({a} + U) g(B \ U),
+// where g(Z), the sum over the set partitions rho of Z of
+// (-1)^|rho| |rho|! prod m(blocks), is the inverse of m under subset convolution
+// (sum_{Y subset Z} m(Y) g(Z \ Y) = 0 for non-empty Z).  With m({a} + U) =
+// m(U) - nu(U) (click; parity -m(U) + 2 (-1)^|U| nu(U)) and nu(U) =
+// sum_{V subset U} s(V) p({a} + V) (Eq. corre_cov_main), the m(U) terms cancel
+// for non-empty B, leaving
+//   click:  c(V) = -s(V) G(B \ V),             G(Z) = sum_{W subset Z} g(W),
+//   parity: c(V) = 2 s(V) (-1)^|B| G'(B \ V),  G'(Z) = sum_{W subset Z} (-1)^|W| g(W),
+// s(V) = (-1)^|V| (click) or (-2)^|V| (parity).
+template <int NB, int CONV>
+__device__ __forceinline__ void cumulant_coefficients(const double (&m)[1 << NB],
+                                                      double (&c)[1 << NB]) {
+  constexpr int NU = 1 << NB;
+  constexpr int FULL = NU - 1;
+  double g[NU];
+  g[0] = 1.0;
+#pragma unroll
+  for (int z = 1; z < NU; ++z) {
+    double acc = 0.0;
+#pragma unroll
+    for (int y = 1; y <= z; ++y)
+      if ((y & z) == y) acc = fma(m[y], g[z ^ y], acc);
+    g[z] = -acc;
+  }
+  if constexpr (CONV != GBS_CLICK) {
+#pragma unroll
+    for (int w = 0; w < NU; ++w)
+      if (popcount_c((unsigned)w) & 1) g[w] = -g[w];
+  }
+#pragma unroll
+  for (int bit = 0; bit < NB; ++bit)
+#pragma unroll
+    for (int w = 0; w < NU; ++w)
+      if (w & (1 << bit)) g[w] += g[w ^ (1 << bit)];
+#pragma unroll
+  for (int v = 0; v < NU; ++v) {
+    const int cv = popcount_c((unsigned)v);
+    const double coef = (CONV == GBS_CLICK) ? ((cv & 1) ? 1.0 : -1.0)
+                                            : (((cv + NB) & 1) ? -2.0 : 2.0) * (double)(1 << cv);
+    c[v] = coef * g[FULL ^ v];
+  }
+}
+
+// The sign s(V) of a vacuum probability p({a} + V) in nu (Eq. corre_cov_main):
+// (-1)^|V| for click, (-2)^|V| for parity.
+template <int CONV>
+__host__ __device__ constexpr double vacuum_sign(int v) {
+  return (CONV == GBS_CLICK) ? ((popcount_c((unsigned)v) & 1) ? -1.0 : 1.0)
+                             : ((popcount_c((unsigned)v) & 1) ? -1.0 : 1.0) *
+                                   (double)(1 << popcount_c((unsigned)v));
+}
+
 // Correlator, cumulant and vacuum probability of the subset s[0] < ... < s[D-1].
 template <int D, int CONV, bool WANT_CUM>
 __device__ __forceinline__ void subset_fp64(const double* __restrict__ Qi, int M, const int (&s)[D],
