@@ -80,13 +80,15 @@ constexpr int kWalkMax = 3 * kGroupGMax + 4;
 
 template <int NB, bool DISP, bool MIXED = false>
 struct GroupLayout {
-  // B's and groups per tile: as many as let three workgroups share a compute
-  // unit's 160 KB of LDS at M = 144 (order 5 at M = 144: FP64 40 -> 52 B's
-  // 5.57 -> 5.27 ms; mixed 40 -> 64 B's 5.22 -> 4.70 ms); the smaller FP32
-  // factor rows and records of the mixed form leave room for a full wavefront
-  // of B's.  kG is a power of two (the record builder's binary search).
-  static constexpr int kB = DISP ? 48 : (MIXED ? 64 : 52);
-  static constexpr int kG = MIXED ? 16 : 8;
+  // B's and groups per tile: as many as let three workgroups (order 5) or four
+  // (orders 3 and 4, whose records are smaller) share a compute unit's 160 KB
+  // of LDS at M = 144 (order 5 at M = 144: FP64 40 -> 52 B's 5.57 -> 5.27 ms;
+  // mixed 40 -> 64 B's 5.22 -> 4.70 ms); the smaller FP32 factor rows and
+  // records of the mixed form leave room for a full wavefront of B's.  kG is
+  // a power of two (the record builder's binary search).
+  static constexpr bool kWide = MIXED || NB < 4;
+  static constexpr int kB = DISP ? 48 : (kWide ? 64 : 52);
+  static constexpr int kG = (kWide && !DISP) ? 16 : 8;
   static_assert(kB <= kGroupBMax && kG <= kGroupGMax && (kG & (kG - 1)) == 0, "tile shape");
   static constexpr int NPm = NB - 2;       // |P|
   static constexpr int NT = NB - 1;        // |T|
@@ -469,9 +471,17 @@ int group_windows_d(int d, int M) {
   }
 }
 
-// Tile shape of the zero-mean plans (the same for every order).
-int plan_kb(bool mixed) { return mixed ? GroupLayout<2, false, true>::kB : GroupLayout<2, false>::kB; }
-int plan_kg(bool mixed) { return mixed ? GroupLayout<2, false, true>::kG : GroupLayout<2, false>::kG; }
+// Tile shape of the zero-mean plans of order d.
+template <int NB>
+int plan_kb_t(bool mixed) { return mixed ? GroupLayout<NB, false, true>::kB : GroupLayout<NB, false>::kB; }
+template <int NB>
+int plan_kg_t(bool mixed) { return mixed ? GroupLayout<NB, false, true>::kG : GroupLayout<NB, false>::kG; }
+int plan_kb(int d, bool mixed) {
+  return d == 3 ? plan_kb_t<2>(mixed) : d == 4 ? plan_kb_t<3>(mixed) : plan_kb_t<4>(mixed);
+}
+int plan_kg(int d, bool mixed) {
+  return d == 3 ? plan_kg_t<2>(mixed) : d == 4 ? plan_kg_t<3>(mixed) : plan_kg_t<4>(mixed);
+}
 
 }  // namespace
 
@@ -488,7 +498,7 @@ bool group_supported(int d, int M, int flags, bool displaced) {
 
 const std::vector<uint64_t>& group_plan_host(int d, int M, bool mixed) {
   const int NB = d - 1;
-  const int kB = plan_kb(mixed), kG = plan_kg(mixed);
+  const int kB = plan_kb(d, mixed), kG = plan_kg(d, mixed);
   std::lock_guard<std::mutex> lock(g_host_plan_mu);
   const PlanKey key{-1, M, NB, kB, kG};
   auto it = g_host_plans.find(key);
@@ -574,7 +584,8 @@ static hipError_t launch_group_c(int M, int flags, const GroupArgs& g, const uin
 
 void group_tiles(int d, int M, bool mixed, std::vector<uint64_t>* out) {
   const int NB = d - 1;
-  const std::vector<uint64_t> t = plan_tiles(M, NB, group_rmax(M, NB), plan_kb(mixed), plan_kg(mixed));
+  const std::vector<uint64_t> t =
+      plan_tiles(M, NB, group_rmax(M, NB), plan_kb(d, mixed), plan_kg(d, mixed));
   out->insert(out->end(), t.begin(), t.end());
 }
 

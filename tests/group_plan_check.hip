@@ -43,7 +43,7 @@ int main() {
     for (int d = 3; d <= 5; ++d) {
       if (d > M || !group_supported(d, M, mixed ? GBS_MIXED : 0, false)) continue;
       const int NB = d - 1, nt = NB - 1;
-      const int kB = plan_kb(mixed != 0), kG = plan_kg(mixed != 0);
+      const int kB = plan_kb(d, mixed != 0), kG = plan_kg(d, mixed != 0);
       const std::vector<uint64_t>& tiles = group_plan_host(d, M, mixed != 0);
       uint64_t beta = 0, subsets = 0;
       for (uint64_t desc : tiles) {
