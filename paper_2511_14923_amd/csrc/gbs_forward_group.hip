@@ -87,7 +87,7 @@ struct GroupLayout {
   // records of the mixed form leave room for a full wavefront of B's.  kG is
   // a power of two (the record builder's binary search).
   static constexpr bool kWide = MIXED || NB < 4;
-  static constexpr int kB = DISP ? 48 : (kWide ? 64 : 52);
+  static constexpr int kB = DISP ? 48 : (kWide ? 64 : 54);
   static constexpr int kG = (kWide && !DISP) ? 16 : 8;
   static_assert(kB <= kGroupBMax && kG <= kGroupGMax && (kG & (kG - 1)) == 0, "tile shape");
   static constexpr int NPm = NB - 2;       // |P|
@@ -114,7 +114,7 @@ struct GroupLayout {
   static constexpr int dMB = dC + NU;           // m(B)
   static constexpr int dZ = dMB + 1;            // displaced: z_{b_0} [2], z_e(B) [2]
   static constexpr int nD = dZ + (DISP ? 4 : 0);
-  static constexpr int nDpad = (nD + 1) & ~1;
+  static constexpr int wOff = nD * 8;          // byte offset of the 32-bit words
   // per-B record, 32-bit words
   static constexpr int wStart = 0;              // first rank of the B-block, tile relative
   static constexpr int wRow = 1;                // byte offset of row 2 b_0 of Q (of E, mixed)
@@ -123,8 +123,13 @@ struct GroupLayout {
   static constexpr int nOP = NP - 2;            // all U containing b_0 except B' and B
   static constexpr int wG = wOP + nOP;          // this B's group (displaced states)
   static constexpr int nW = wG + (DISP ? 1 : 0);
-  static constexpr int nWpad = (nW + 3) & ~3;
-  static constexpr int bytes = nDpad * 8 + nWpad * 4;
+
+  // record stride: whole 16-byte units (16-byte LDS reads in phase 2), an odd
+  // number of them, so that the lane-per-B accesses of the setup phases (lane
+  // c at c * bytes) spread over the 32 LDS banks; an even number at least
+  // doubles their bank conflicts (order 5 FP64: 22 units, 16-way)
+  static constexpr int bytes0 = (wOff + nW * 4 + 15) & ~15;
+  static constexpr int bytes = ((bytes0 / 16) % 2 == 0) ? bytes0 + 16 : bytes0;
   // (T, a) record in 16-byte units, unit q of record i at [q][i], so that
   // consecutive records (consecutive a across a wavefront) fall in consecutive
   // LDS banks.  FP64: y_P row k is unit uY + k (two columns); mixed: unit
