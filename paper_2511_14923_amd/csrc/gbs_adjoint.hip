@@ -170,6 +170,16 @@ struct Offsets {
   int64_t off[kMaxOrder + 2];  // start of order-d block, off[1] = 0
 };
 
+// A superset sum of n terms split over nsplit workgroups (blockIdx.y): chunk y
+// takes the terms [n y / nsplit, n (y + 1) / nsplit).  With nsplit > 1 each
+// workgroup writes its partial sum to part[(item * nsplit + y) * width + e] and
+// a finishing kernel adds the partials in chunk order, so the result stays
+// deterministic for a given launch shape.
+__device__ __forceinline__ void chunk_range(uint64_t n, uint64_t* lo, uint64_t* hi) {
+  *lo = n * blockIdx.y / gridDim.y;
+  *hi = n * (blockIdx.y + 1) / gridDim.y;
+}
+
 // ---------------------------------------------------------------------------
 // D1(X) for every non-empty X with |X| <= K - 1 (one thread per X).
 __global__ void d1_kernel(const double* __restrict__ m, int M, int K, Offsets o,
@@ -209,15 +219,17 @@ __global__ __launch_bounds__(kSumThreads) void mbar_kernel(int M, int K, int k, 
                                                      const double* __restrict__ gm,
                                                      const double* __restrict__ gk,
                                                      const double* __restrict__ d1,
-                                                     double* __restrict__ mbar) {
+                                                     double* __restrict__ mbar,
+                                                     double* __restrict__ part) {
   const uint64_t rb = blockIdx.x;
   int B[kMaxOrder];
   unrank_dyn(bin, rb, k, M, B);
   double acc = 0.0;
   if (gk && k < K) {
     const int u = M - k;
-    const uint64_t nx = count_sized(bin, 1, K - k, u);
-    for (uint64_t i = threadIdx.x; i < nx; i += blockDim.x) {
+    uint64_t lo, hi;
+    chunk_range(count_sized(bin, 1, K - k, u), &lo, &hi);
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
       int j;
       uint64_t rx;
       flat_to_sized(bin, i, 1, K - k, u, &j, &rx);
@@ -230,12 +242,30 @@ __global__ __launch_bounds__(kSumThreads) void mbar_kernel(int M, int K, int k, 
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) {
+    if (gridDim.y > 1) {
+      part[rb * gridDim.y + blockIdx.y] = acc;
+      return;
+    }
     const int64_t at = o.off[k] + (int64_t)rb;
     double v = acc;
     if (gk) v += gk[at];
     if (gm) v += gm[at];
     mbar[at] = v;
   }
+}
+
+// The split mbar sums of order k: partials in chunk order, then as mbar_kernel.
+__global__ void mbar_finish_kernel(int k, int nsplit, uint64_t count, Offsets o,
+                                   const double* __restrict__ gm, const double* __restrict__ gk,
+                                   const double* __restrict__ part, double* __restrict__ mbar) {
+  const uint64_t rb = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rb >= count) return;
+  double v = 0.0;
+  for (int y = 0; y < nsplit; ++y) v += part[rb * nsplit + y];
+  const int64_t at = o.off[k] + (int64_t)rb;
+  if (gk) v += gk[at];
+  if (gm) v += gm[at];
+  mbar[at] = v;
 }
 
 // The top order K has no proper supersets: mbar = gk + gm and
@@ -260,14 +290,16 @@ __global__ void top_order_kernel(int64_t off, uint64_t count, int K, int parity,
 __global__ __launch_bounds__(kSumThreads) void pbar_kernel(int M, int K, int t, int parity, Offsets o,
                                                      const uint64_t* __restrict__ bin,
                                                      const double* __restrict__ mbar,
-                                                     double* __restrict__ pbar) {
+                                                     double* __restrict__ pbar,
+                                                     double* __restrict__ part) {
   const uint64_t rt = blockIdx.x;
   int T[kMaxOrder];
   unrank_dyn(bin, rt, t, M, T);
   const int u = M - t;
-  const uint64_t nx = count_sized(bin, 0, K - t, u);
+  uint64_t lo, hi;
+  chunk_range(count_sized(bin, 0, K - t, u), &lo, &hi);
   double acc = 0.0;
-  for (uint64_t i = threadIdx.x; i < nx; i += blockDim.x) {
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     int j;
     uint64_t rx;
     flat_to_sized(bin, i, 0, K - t, u, &j, &rx);
@@ -280,11 +312,27 @@ __global__ __launch_bounds__(kSumThreads) void pbar_kernel(int M, int K, int t, 
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) {
+    if (gridDim.y > 1) {
+      part[rt * gridDim.y + blockIdx.y] = acc;
+      return;
+    }
     // click: (-1)^t;  parity: (-2)^t (the (-1)^|B| factor is inside the sum)
     double coef = (t & 1) ? -1.0 : 1.0;
     if (parity) coef *= (double)(1 << t);
     pbar[o.off[t] + (int64_t)rt] = coef * acc;
   }
+}
+
+// The split pbar sums of order t: partials in chunk order, then as pbar_kernel.
+__global__ void pbar_finish_kernel(int t, int parity, int nsplit, uint64_t count, Offsets o,
+                                   const double* __restrict__ part, double* __restrict__ pbar) {
+  const uint64_t rt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rt >= count) return;
+  double v = 0.0;
+  for (int y = 0; y < nsplit; ++y) v += part[rt * nsplit + y];
+  double coef = (t & 1) ? -1.0 : 1.0;
+  if (parity) coef *= (double)(1 << t);
+  pbar[o.off[t] + (int64_t)rt] = coef * v;
 }
 
 // Trailing (base) block of Q_T^{-1}: the first NX blocks of `modes` are
@@ -387,6 +435,38 @@ __device__ __forceinline__ void base_inverse_dispatch(const double* __restrict__
   }
 }
 
+// Mode pair of a sigma-bar item: the diagonal pairs (i, i), or the pairs i < j
+// in colex order (item j (j - 1) / 2 + i).
+__device__ __forceinline__ void pair_of(int64_t pid, int diag, int* pi_, int* pj_) {
+  if (diag) {
+    *pi_ = *pj_ = (int)pid;
+    return;
+  }
+  int j = (int)((1.0 + sqrt(8.0 * (double)pid + 1.0)) / 2.0);
+  while ((int64_t)j * (j - 1) / 2 > pid) --j;
+  while ((int64_t)(j + 1) * j / 2 <= pid) ++j;
+  *pi_ = (int)(pid - (int64_t)j * (j - 1) / 2);
+  *pj_ = j;
+}
+
+// The 2x2 block (i, j) of dL/dsigma (interleaved (2i + a, 2j + b) -> xxpp
+// (i + a M, j + b M)) and, for i != j, its mirror.
+__device__ __forceinline__ void store_sigma_block(double* __restrict__ gsig, int M, int i, int j,
+                                                  const double (&acc)[4]) {
+  const size_t n2 = 2 * (size_t)M;
+  const size_t xi = i, pi = i + M, xj = j, pj = j + M;
+  gsig[xi * n2 + xj] = acc[0];
+  gsig[xi * n2 + pj] = acc[1];
+  gsig[pi * n2 + xj] = acc[2];
+  gsig[pi * n2 + pj] = acc[3];
+  if (i != j) {
+    gsig[xj * n2 + xi] = acc[0];
+    gsig[pj * n2 + xi] = acc[1];
+    gsig[xj * n2 + pi] = acc[2];
+    gsig[pj * n2 + pi] = acc[3];
+  }
+}
+
 // One wavefront per mode pair (i <= j): the 2x2 block of dL/dsigma.
 // One workgroup per mode pair (i, j): the diagonal pairs (many more supersets,
 // wide workgroups) and the pairs i < j (colex, blockIdx = j (j - 1) / 2 + i)
@@ -397,24 +477,19 @@ __global__ __launch_bounds__(kSigmaThreads) void sigma_bar_kernel(const double* 
                                                                 const double* __restrict__ ptab,
                                                                 const double* __restrict__ pbar,
                                                                 double* __restrict__ gsig,
-                                                                DeviceStatus* __restrict__ st) {
+                                                                DeviceStatus* __restrict__ st,
+                                                                double* __restrict__ part) {
   const int64_t pid = blockIdx.x;
   int i, j;
-  if (diag) {
-    i = j = (int)pid;
-  } else {
-    j = (int)((1.0 + sqrt(8.0 * (double)pid + 1.0)) / 2.0);
-    while ((int64_t)j * (j - 1) / 2 > pid) --j;
-    while ((int64_t)(j + 1) * j / 2 <= pid) ++j;
-    i = (int)(pid - (int64_t)j * (j - 1) / 2);
-  }
+  pair_of(pid, diag, &i, &j);
   int base[2] = {i, j};
   const int nb = (i == j) ? 1 : 2;
   const int u = M - nb;
-  const uint64_t nx = count_sized(bin, 0, K - nb, u);
+  uint64_t lo, hi;
+  chunk_range(count_sized(bin, 0, K - nb, u), &lo, &hi);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   bool bad = false;
-  for (uint64_t q = threadIdx.x; q < nx; q += blockDim.x) {
+  for (uint64_t q = lo + threadIdx.x; q < hi; q += blockDim.x) {
     int jx;
     uint64_t rx;
     flat_to_sized(bin, q, 0, K - nb, u, &jx, &rx);
@@ -436,21 +511,26 @@ __global__ __launch_bounds__(kSigmaThreads) void sigma_bar_kernel(const double* 
 #pragma unroll
   for (int e = 0; e < 4; ++e) acc[e] = block_sum(acc[e]);
   if (bad) latch_failure(st, 0, (int64_t)j * (j + 1) / 2 + i);  // pair index, i <= j
-  if (threadIdx.x == 0) {
-    const size_t n2 = 2 * (size_t)M;
-    // interleaved (2i + a, 2j + b) -> xxpp (i + a M, j + b M)
-    const size_t xi = i, pi = i + M, xj = j, pj = j + M;
-    gsig[xi * n2 + xj] = acc[0];
-    gsig[xi * n2 + pj] = acc[1];
-    gsig[pi * n2 + xj] = acc[2];
-    gsig[pi * n2 + pj] = acc[3];
-    if (i != j) {
-      gsig[xj * n2 + xi] = acc[0];
-      gsig[pj * n2 + xi] = acc[1];
-      gsig[xj * n2 + pi] = acc[2];
-      gsig[pj * n2 + pi] = acc[3];
-    }
+  if (threadIdx.x == 0 && gridDim.y > 1) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) part[((size_t)pid * gridDim.y + blockIdx.y) * 4 + e] = acc[e];
+  } else if (threadIdx.x == 0) {
+    store_sigma_block(gsig, M, i, j, acc);
   }
+}
+
+// The split sigma-bar sums: partials in chunk order, then as sigma_bar_kernel.
+__global__ void sigma_finish_kernel(int M, int diag, int nsplit, uint64_t count,
+                                    const double* __restrict__ part, double* __restrict__ gsig) {
+  const uint64_t pid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pid >= count) return;
+  int i, j;
+  pair_of((int64_t)pid, diag, &i, &j);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int y = 0; y < nsplit; ++y)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[e] += part[(pid * nsplit + y) * 4 + e];
+  store_sigma_block(gsig, M, i, j, acc);
 }
 
 }  // namespace
@@ -458,7 +538,7 @@ __global__ __launch_bounds__(kSigmaThreads) void sigma_bar_kernel(const double* 
 hipError_t launch_adjoint(int M, int K, int flags, const double* Qi, const uint64_t* binom,
                           const double* m, const double* ptab, const double* gm, const double* gk,
                           double* d1, double* mbar, double* pbar, double* gsig, DeviceStatus* st,
-                          hipStream_t s) {
+                          double* part, hipStream_t s) {
   Offsets o{};
   o.off[1] = 0;
   for (int d = 1; d <= kMaxOrder; ++d) o.off[d + 1] = o.off[d] + (d <= K ? (int64_t)host_binom(M, d) : 0);
@@ -483,12 +563,27 @@ hipError_t launch_adjoint(int M, int K, int flags, const double* Qi, const uint6
     for (int j = jmin; j <= K - k; ++j) n += host_binom(M - k, j);
     return n;
   };
+  // workgroups per sum: a launch of fewer than kAdjointSplitItems long sums
+  // (the order-1 subsets, the diagonal mode pairs) would leave compute units
+  // idle, so each sum is split into chunks of at least 512 terms
+  auto split_for = [](uint64_t items, uint64_t n) -> unsigned {
+    if (items >= (uint64_t)kAdjointSplitItems) return 1u;
+    const uint64_t want = ((uint64_t)kAdjointSplitItems + items - 1) / items;
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>({want, (uint64_t)kAdjointMaxSplit, n / 512}));
+  };
+  auto finish_grid = [](uint64_t items) { return dim3((unsigned)((items + 255) / 256)); };
   for (int k = 1; k < K && e == hipSuccess; ++k) {
     e = timing_begin(s, GBS_STAGE_ADJOINT, k);
+    const uint64_t items = host_binom(M, k), n = supersets(k, 1);
+    const unsigned ns = gk ? split_for(items, n) : 1u;
     if (e == hipSuccess)
-      hipLaunchKernelGGL(mbar_kernel, dim3((unsigned)host_binom(M, k)),
-                         dim3(gk ? threads_for(supersets(k, 1)) : kWave), 0, s, M, K, k, o, binom,
-                         gm, gk, d1, mbar);
+      hipLaunchKernelGGL(mbar_kernel, dim3((unsigned)items, ns),
+                         dim3(gk ? threads_for((n + ns - 1) / ns) : kWave), 0, s, M, K, k, o,
+                         binom, gm, gk, d1, mbar, part);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess && ns > 1)
+      hipLaunchKernelGGL(mbar_finish_kernel, finish_grid(items), dim3(256), 0, s, k, (int)ns,
+                         items, o, gm, gk, part, mbar);
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = timing_end(s);
   }
@@ -503,10 +598,15 @@ hipError_t launch_adjoint(int M, int K, int flags, const double* Qi, const uint6
   }
   for (int t = 1; t < K && e == hipSuccess; ++t) {
     e = timing_begin(s, GBS_STAGE_ADJOINT, t);
+    const uint64_t items = host_binom(M, t), n = supersets(t, 0);
+    const unsigned ns = split_for(items, n);
     if (e == hipSuccess)
-      hipLaunchKernelGGL(pbar_kernel, dim3((unsigned)host_binom(M, t)),
-                         dim3(threads_for(supersets(t, 0))), 0, s, M, K, t, parity, o, binom, mbar,
-                         pbar);
+      hipLaunchKernelGGL(pbar_kernel, dim3((unsigned)items, ns), dim3(threads_for((n + ns - 1) / ns)),
+                         0, s, M, K, t, parity, o, binom, mbar, pbar, part);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess && ns > 1)
+      hipLaunchKernelGGL(pbar_finish_kernel, finish_grid(items), dim3(256), 0, s, t, parity,
+                         (int)ns, items, o, part, pbar);
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = timing_end(s);
   }
@@ -518,17 +618,20 @@ hipError_t launch_adjoint(int M, int K, int flags, const double* Qi, const uint6
       for (int q = 0; q <= K - nb; ++q) n += host_binom(M - nb, q);
       return n;
     };
-    if (e == hipSuccess)
-      hipLaunchKernelGGL(sigma_bar_kernel, dim3((unsigned)M),
-                         dim3(threads_for(sets(1), kSigmaThreads)), 0, s, Qi, M, K, 1, o, binom,
-                         ptab, pbar, gsig, st);
-    if (e == hipSuccess) e = hipGetLastError();
-    const unsigned pairs = (unsigned)((int64_t)M * (M - 1) / 2);
-    if (e == hipSuccess && pairs > 0)
-      hipLaunchKernelGGL(sigma_bar_kernel, dim3(pairs),
-                         dim3(threads_for(sets(2), kSigmaThreads)), 0, s, Qi, M, K, 0, o, binom,
-                         ptab, pbar, gsig, st);
-    if (e == hipSuccess) e = hipGetLastError();
+    for (int diag = 1; diag >= 0 && e == hipSuccess; --diag) {
+      const uint64_t items = diag ? (uint64_t)M : (uint64_t)M * (M - 1) / 2;
+      if (items == 0) continue;
+      const uint64_t n = sets(diag ? 1 : 2);
+      const unsigned ns = split_for(items, n);
+      hipLaunchKernelGGL(sigma_bar_kernel, dim3((unsigned)items, ns),
+                         dim3(threads_for((n + ns - 1) / ns, kSigmaThreads)), 0, s, Qi, M, K, diag,
+                         o, binom, ptab, pbar, gsig, st, part);
+      e = hipGetLastError();
+      if (e == hipSuccess && ns > 1)
+        hipLaunchKernelGGL(sigma_finish_kernel, finish_grid(items), dim3(256), 0, s, M, diag,
+                           (int)ns, items, part, gsig);
+      if (e == hipSuccess) e = hipGetLastError();
+    }
     if (e == hipSuccess) e = timing_end(s);
   }
   return e;

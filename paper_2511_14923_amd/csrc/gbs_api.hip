@@ -361,6 +361,7 @@ gbs_status run_adjoint(int32_t M, const double* sigma, int32_t K, int32_t flags,
   const size_t oMb = off; off += align256(N * sizeof(double));
   const size_t oPb = off; off += align256(N * sizeof(double));
   const size_t oSt = off; off += align256(sizeof(DeviceStatus));
+  const size_t oPart = off; off += align256(kAdjointPartDoubles * sizeof(double));
   void* scratch = nullptr;
   e = hipMallocAsync(&scratch, off, s);
   if (e != hipSuccess) return to_status(e);
@@ -368,6 +369,7 @@ gbs_status run_adjoint(int32_t M, const double* sigma, int32_t K, int32_t flags,
   double* Qi = reinterpret_cast<double*>(b + oQ);
   double* Qd = reinterpret_cast<double*>(b + oQd);
   double* ptab = reinterpret_cast<double*>(b + oP);
+  double* part = reinterpret_cast<double*>(b + oPart);
   double* m = reinterpret_cast<double*>(b + oM);
   double* d1 = reinterpret_cast<double*>(b + oD);
   double* mbar = reinterpret_cast<double*>(b + oMb);
@@ -395,7 +397,8 @@ gbs_status run_adjoint(int32_t M, const double* sigma, int32_t K, int32_t flags,
     if (e == hipSuccess) e = timing_end(s);
   }
   if (e == hipSuccess)
-    e = launch_adjoint(M, K, flags, Qi, ctx->binom, m, ptab, gm, gk, d1, mbar, pbar, gsig, st, s);
+    e = launch_adjoint(M, K, flags, Qi, ctx->binom, m, ptab, gm, gk, d1, mbar, pbar, gsig, st, part,
+                       s);
   if (e != hipSuccess) {
     (void)hipFreeAsync(scratch, s);
     return to_status(e);

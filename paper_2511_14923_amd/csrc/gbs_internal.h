@@ -171,11 +171,16 @@ hipError_t launch_forward_rec(int d, int M, int flags, const double* Qi, const d
 
 // Vector-Jacobian product given the forward correlators m and vacuum
 // probabilities ptab of every subset (orders 1..K); d1, mbar, pbar are scratch
-// of N(M, K) doubles; gsig (2M x 2M, xxpp) is overwritten.
+// of N(M, K) doubles, part scratch of kAdjointPartDoubles doubles (the partial
+// sums of superset sums split over several workgroups); gsig (2M x 2M, xxpp)
+// is overwritten.
+constexpr int kAdjointSplitItems = 2048;  // a launch of fewer sums splits each one
+constexpr int kAdjointMaxSplit = 16;
+constexpr size_t kAdjointPartDoubles = 4 * 2 * (size_t)kAdjointSplitItems;
 hipError_t launch_adjoint(int M, int K, int flags, const double* Qi, const uint64_t* binom,
                           const double* m, const double* ptab, const double* gm, const double* gk,
                           double* d1, double* mbar, double* pbar, double* gsig, DeviceStatus* st,
-                          hipStream_t s);
+                          double* part, hipStream_t s);
 
 // Stage-2 sampler (gbs_sampler.hip): nsamples patterns of M bits from the
 // parity cumulants kap (orders 1..K, K = 3 or 5), uniforms u (M x nsamples),
