@@ -228,8 +228,23 @@ def batched_and_adjoint(P, torch, G, steps):
         key = f"{st}{order}" if st != "build_q" else st
         stages[key] = stages.get(key, 0.0) + ms
     wall = sorted(walls)[len(walls) // 2]
+    # algorithmic work of one gradient: the forward tables, then per subset T of
+    # order d the inverse of Q_T ((2d)^3) weighted into the covariance gradient
+    # (2 (2d)^2), and two flops per (subset, proper superset) pair for the
+    # correlator and probability adjoints
+    K3 = 3
+    fl = sum(math.comb(144, d) * (FLOPS_PER_SUBSET[d] + (2 * d) ** 3 + 2 * (2 * d) ** 2)
+             for d in range(1, K3 + 1))
+    fl += 2 * 2 * sum(math.comb(144, d) * sum(math.comb(144 - d, j) for j in range(1, K3 - d + 1))
+                      for d in range(1, K3))
     out["grad_m144_k3"] = {"subsets": n, "ms_per_call": 1e3 * wall,
-                           "gradients_per_s": 1.0 / wall, "stage_ms": stages}
+                           "gradients_per_s": 1.0 / wall, "stage_ms": stages,
+                           "roofline": {"bound": "alu", "achieved": fl / wall / 1e12,
+                                        "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                                        "frac": fl / wall / 1e12 / PEAK_VALU_TFLOPS,
+                                        "algorithmic_flops": fl,
+                                        "note": "wall time per call, nine launches of "
+                                                "small grids: launch and latency bound"}}
     return out
 
 
