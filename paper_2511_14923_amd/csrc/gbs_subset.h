@@ -136,8 +136,8 @@ __device__ __forceinline__ double cumulant_from_correlators(const double (&m)[1 
 //   parity: c(V) = 2 s(V) (-1)^|B| G'(B \ V),  G'(Z) = sum_{W subset Z} (-1)^|W| g(W),
 // s(V) = (-1)^|V| (click) or (-2)^|V| (parity).
 template <int NB, int CONV>
-__device__ __forceinline__ void cumulant_coefficients(const double (&m)[1 << NB],
-                                                      double (&c)[1 << NB]) {
+__host__ __device__ __forceinline__ void cumulant_coefficients(const double (&m)[1 << NB],
+                                                               double (&c)[1 << NB]) {
   constexpr int NU = 1 << NB;
   constexpr int FULL = NU - 1;
   double g[NU];
