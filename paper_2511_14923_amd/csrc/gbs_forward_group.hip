@@ -242,9 +242,7 @@ __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(1
   const int ld = M + 1;
   uint64_t* bits = reinterpret_cast<uint64_t*>(bin + (((D + 1) * ld + 1) & ~1));
   unsigned char* first = reinterpret_cast<unsigned char*>(bits + nwin_max);
-  __shared__ uint32_t s_ntile, s_r0, s_ngroups, s_nrec;
-  __shared__ uint32_t s_gbase[GL::kG];      // first (T, a) record of each group
-  __shared__ int s_gT[GL::kG][NB - 1];       // modes of T, in the order P, e
+  __shared__ uint32_t s_ntile, s_r0;
 
   for (int i = threadIdx.x; i < (D + 1) * ld; i += blockDim.x) {
     const int kk = i / ld, nn = i - kk * ld;
@@ -294,9 +292,7 @@ __global__ __launch_bounds__(kGroupThreads) void forward_group_batched_kernel(
   const int ld = max_M + 1;
   uint64_t* bits = reinterpret_cast<uint64_t*>(bin + (((D + 1) * ld + 1) & ~1));
   unsigned char* first = reinterpret_cast<unsigned char*>(bits + nwin_max);
-  __shared__ uint32_t s_ntile, s_r0, s_ngroups, s_nrec;
-  __shared__ uint32_t s_gbase[GL::kG];
-  __shared__ int s_gT[GL::kG][NB - 1];
+  __shared__ uint32_t s_ntile, s_r0;
   __shared__ uint32_t s_item;
 
   for (int i = threadIdx.x; i < (D + 1) * ld; i += blockDim.x) {
