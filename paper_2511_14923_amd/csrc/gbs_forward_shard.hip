@@ -123,9 +123,9 @@ __device__ __forceinline__ void a_tree(const double* rec, const double (&C)[2 * 
   const double w01 = fma(i00, C[0][1], i10 * C[1][1]);
   const double w10 = fma(i10, C[0][0], i11 * C[1][0]);
   const double w11 = fma(i10, C[0][1], i11 * C[1][1]);
-  const double t00 = s00 - fma(C[0][0], w00, C[1][0] * w10);
-  const double t10 = s10 - fma(C[0][1], w00, C[1][1] * w10);
-  const double t11 = s11 - fma(C[0][1], w01, C[1][1] * w11);
+  const double t00 = fma(-C[0][0], w00, fma(-C[1][0], w10, s00));
+  const double t10 = fma(-C[0][1], w00, fma(-C[1][1], w10, s10));
+  const double t11 = fma(-C[0][1], w01, fma(-C[1][1], w11, s11));
   if constexpr (n == 2) {
     a_leaf<NB, MASK | (1u << K)>(rec, t00, t10, t11, pa, bad);
     a_leaf<NB, MASK>(rec, s00, s10, s11, pa, bad);
@@ -135,7 +135,7 @@ __device__ __forceinline__ void a_tree(const double* rec, const double (&C)[2 * 
     for (int j = 0; j < n - 2; ++j) {
       const double u0 = nd[3 + j], u1 = nd[3 + (n - 2) + j];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) Ce[j][c] = C[2 + j][c] - fma(u0, C[0][c], u1 * C[1][c]);
+      for (int c = 0; c < 2; ++c) Ce[j][c] = fma(-u0, C[0][c], fma(-u1, C[1][c], C[2 + j][c]));
     }
     a_tree<NB, K + 1, MASK | (1u << K)>(rec, Ce, t00, t10, t11, pa, bad);
     double Cr[n - 2][2];
@@ -148,11 +148,13 @@ __device__ __forceinline__ void a_tree(const double* rec, const double (&C)[2 * 
   }
 }
 
-// Four waves per SIMD: the per-subset recursion would take 160 VGPRs (three
-// waves); capped at 128 it spills four, and the extra wave hides more of the
-// Q and LDS latency.
+// Three waves per SIMD (168 VGPRs, no spills): with its updates written as
+// fused multiply-add chains the per-subset recursion issues 581 instead of 670
+// VALU instructions, and a cap of 128 registers for a fourth wave now fails in
+// the compiler's spill code (the earlier form ran four waves with four
+// registers spilled, 2% slower than this).
 template <int D, int CONV, bool WC, bool WK>
-__global__ __launch_bounds__(kShardThreads) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kShardThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void forward_shard_kernel(
     const double* __restrict__ Qi, int M, uint64_t rank0, uint64_t count, uint64_t beta0,
     uint64_t nbeta, uint64_t ntiles, const uint64_t* __restrict__ binom,
