@@ -37,7 +37,7 @@ PEAK_HBM_BYTES = 8e12
 
 
 # the sources the order-5 kernel of the headline path is compiled from
-TRAFFIC_SOURCES = ("gbs_device.h", "gbs_forward_group.hip", "gbs_group_tile.inc")
+TRAFFIC_SOURCES = ("gbs_device.h", "gbs_subset.h", "gbs_forward_group.hip", "gbs_group_tile.inc")
 
 
 def kernel_source_hash(sources=TRAFFIC_SOURCES) -> str:

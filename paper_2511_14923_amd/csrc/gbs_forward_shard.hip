@@ -152,7 +152,7 @@ __device__ __forceinline__ void a_tree(const double* rec, const double (&C)[2 * 
 // fused multiply-add chains the per-subset recursion issues 581 instead of 670
 // VALU instructions, and a cap of 128 registers for a fourth wave now fails in
 // the compiler's spill code (the earlier form ran four waves with four
-// registers spilled, 2% slower than this).
+// registers spilled, about 1% slower than this).
 template <int D, int CONV, bool WC, bool WK>
 __global__ __launch_bounds__(kShardThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void forward_shard_kernel(
