@@ -308,8 +308,13 @@ void forward_shard_kernel(
 // Per subset that is 2^|T| - 1 cross-block updates and 2^|T| 2x2
 // determinants; the half of the 2^|B| probabilities that does not contain b_0
 // is shared by all the b_0 of a lane.
-constexpr int kTsA = 64;  // a's per tile: one wavefront
-constexpr int kTsB = 24;  // b_0's per tile
+// a's per tile: one wavefront.  b_0's per tile: 30 records (19.1 KB of LDS at
+// order 5) let the eight one-wavefront workgroups that the order-5 kernel's 246
+// VGPRs allow share a compute unit (M = 1152 order-5 shard: 16 / 24 / 30 / 32
+// b_0's 8.3 / 8.1 / 7.8 / 7.8 ms; capping the registers for a third wave per
+// SIMD spills and takes 25 ms).
+constexpr int kTsA = 64;
+constexpr int kTsB = 30;
 
 // One T of the rank range (host-built list, in colex order of T).
 struct ShardT {
