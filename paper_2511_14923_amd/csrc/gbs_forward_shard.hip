@@ -1,6 +1,8 @@
-// B-tiled kernel for one colex rank range of one order (3..5) from Q alone.
+// Kernels for one colex rank range of one order (3..5) from Q alone: the
+// T-shared kernel (below, the default) and the B-tiled kernel it replaced,
+// which still takes ranges of more than kTsMaxT T's.
 //
-// The subsets S = {a} + B with a < b_0 = min B are consecutive colex ranks,
+// B-tiled kernel.  The subsets S = {a} + B with a < b_0 = min B are consecutive colex ranks,
 // rank(S) = a + sum_j C(b_j, j + 2), so a rank range is a run of B's, partial
 // at its two ends.  A workgroup takes up to kShardB consecutive B's and splits
 // the principal-minor work of each subset into what depends on B alone and what

@@ -37,7 +37,7 @@ def _dev(x):
 def test_shard_is_a_slice_of_the_full_pass(P, conv):
     """Ranges at the start, inside and at the end of order 5 (partial B runs at
     both ends): with GBS_ALL_MINORS the shard runs the all-minors kernel of the
-    full pass and its outputs are the same bits; the default B-tiled kernel
+    full pass and its outputs are the same bits; the default T-shared kernel
     agrees with the full pass to FP64 rounding and with the oracle."""
     import torch
     _say("case: shard slice M=40", conv)
