@@ -209,10 +209,11 @@ GBS_API gbs_status gbs_cumulants_displaced(int32_t M, const double* sigma, const
  * devices for large M (e.g. M = 1152 pseudo-photon-number-resolving detection,
  * C(1152, 5) = 1.7e13 order-5 subsets).  Orders 3..5 run the T-shared kernel
  * (the subsets {a, b_0} + T of one T share the factors of Q_T, of each b_0
- * and of each a against T; App. D.1, Eq. vacuum_gaussian_prob), whose host
- * side lists the range's T's on the first call of a range and keeps the last
- * eight lists on the device (evicting one waits for the device); ranges of
- * more than 2^22 T's run the B-tiled kernel.  Orders 1, 2 and GBS_ALL_MINORS
+ * and of each a against T; App. D.1, Eq. vacuum_gaussian_prob).  Its host
+ * side lists the range's T's on the first call of a range and copies the list
+ * to the device with a blocking copy (so that first call must not be captured
+ * in a graph); the last eight lists stay on the device, and evicting one waits
+ * for the device.  Ranges of more than 2^22 T's run the B-tiled kernel.  Orders 1, 2 and GBS_ALL_MINORS
  * run the all-minors kernel of gbs_cumulants' GBS_ALL_MINORS, whose shards are
  * bit-identical to slices of that full pass.
  * Same definitions and tolerance as gbs_cumulants.

@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <cmath>
 #include <list>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -744,8 +745,10 @@ bool ts_build(int d, int M, uint64_t rank0, uint64_t count, std::vector<ShardT>&
   return !out.empty();
 }
 
-// Device copies of recent T lists, most recent first (evicting one frees its
-// buffer, which waits for the device).
+// Device copies of recent T lists, most recent first.  A caller holds its list
+// by shared pointer until its launch is enqueued, so a list evicted meanwhile
+// by another thread is freed only after that (hipFree waits for the device).
+// The cache itself is never destroyed (no frees at process exit).
 struct TsKey {
   int device, d, M;
   uint64_t rank0, count;
@@ -756,46 +759,52 @@ struct TsKey {
 struct TsPlan {
   ShardT* dev = nullptr;
   uint32_t nT = 0, ntiles = 0;
+  TsPlan() = default;
+  TsPlan(const TsPlan&) = delete;
+  TsPlan& operator=(const TsPlan&) = delete;
+  ~TsPlan() {
+    if (dev) (void)hipFree(dev);
+  }
 };
 constexpr size_t kTsCache = 8;
 std::mutex g_ts_mu;
-std::list<std::pair<TsKey, TsPlan>> g_ts;
+auto& g_ts = *new std::list<std::pair<TsKey, std::shared_ptr<TsPlan>>>();
 
-hipError_t ts_plan(int d, int M, uint64_t rank0, uint64_t count, TsPlan* out, bool* ok) {
-  *ok = false;
+// The T list of a range (cached), or null when the B-tiled kernel takes it.
+hipError_t ts_plan(int d, int M, uint64_t rank0, uint64_t count, std::shared_ptr<TsPlan>* out) {
+  out->reset();
   int device = 0;
   hipError_t e = hipGetDevice(&device);
   if (e != hipSuccess) return e;
   const TsKey key{device, d, M, rank0, count};
+  std::shared_ptr<TsPlan> evicted;  // released after the lock
   std::lock_guard<std::mutex> lock(g_ts_mu);
   for (auto it = g_ts.begin(); it != g_ts.end(); ++it) {
     if (it->first == key) {
       g_ts.splice(g_ts.begin(), g_ts, it);
       *out = g_ts.front().second;
-      *ok = true;
       return hipSuccess;
     }
   }
   std::vector<ShardT> host;
   uint32_t ntiles = 0;
   if (!ts_build(d, M, rank0, count, host, &ntiles)) return hipSuccess;
-  TsPlan p;
-  p.nT = (uint32_t)host.size();
-  p.ntiles = ntiles;
-  e = hipMalloc(&p.dev, host.size() * sizeof(ShardT));
-  if (e != hipSuccess) return e;
-  e = hipMemcpy(p.dev, host.data(), host.size() * sizeof(ShardT), hipMemcpyHostToDevice);
+  auto p = std::make_shared<TsPlan>();
+  p->nT = (uint32_t)host.size();
+  p->ntiles = ntiles;
+  e = hipMalloc(&p->dev, host.size() * sizeof(ShardT));
   if (e != hipSuccess) {
-    (void)hipFree(p.dev);
+    p->dev = nullptr;
     return e;
   }
+  e = hipMemcpy(p->dev, host.data(), host.size() * sizeof(ShardT), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
   g_ts.emplace_front(key, p);
   if (g_ts.size() > kTsCache) {
-    (void)hipFree(g_ts.back().second.dev);
+    evicted = std::move(g_ts.back().second);
     g_ts.pop_back();
   }
   *out = p;
-  *ok = true;
   return hipSuccess;
 }
 
@@ -817,11 +826,10 @@ hipError_t launch_forward_shard(int d, int M, int flags, const double* Qi, const
   if (count == 0 || (!corr && !cum)) return hipSuccess;
   if (d < 3 || d > kMaxOrder) return hipErrorInvalidValue;
   {
-    TsPlan tp;
-    bool ok = false;
-    const hipError_t e = ts_plan(d, M, rank0, count, &tp, &ok);
+    std::shared_ptr<TsPlan> tp;
+    const hipError_t e = ts_plan(d, M, rank0, count, &tp);
     if (e != hipSuccess) return e;
-    if (ok) {
+    if (tp) {
       using TsLaunch = hipError_t (*)(int, const double*, uint64_t, const ShardT*, uint32_t,
                                       uint32_t, double*, double*, DeviceStatus*, hipStream_t);
       const bool par = (flags & GBS_PARITY) != 0;
@@ -831,7 +839,7 @@ hipError_t launch_forward_shard(int d, int M, int flags, const double* Qi, const
         case 4: fn = par ? launch_tshard_t<4, GBS_PARITY> : launch_tshard_t<4, GBS_CLICK>; break;
         default: fn = par ? launch_tshard_t<5, GBS_PARITY> : launch_tshard_t<5, GBS_CLICK>; break;
       }
-      return fn(M, Qi, rank0, tp.dev, tp.nT, tp.ntiles, corr, cum, st, s);
+      return fn(M, Qi, rank0, tp->dev, tp->nT, tp->ntiles, corr, cum, st, s);
     }
   }
   const uint64_t beta0 = top_rank(d, rank0);

@@ -121,3 +121,39 @@ def test_pseudo_pnr_m1152(P, pnr, order, where):
     smu, skap = fp64_scales(pnr, order, ranks)
     assert_within(c.cpu().numpy()[local], rc, fp64_tolerance(rc, smu), f"M=1152 d={order} corr")
     assert_within(k.cpu().numpy()[local], rk, fp64_tolerance(rk, skap), f"M=1152 d={order} cum")
+
+
+def test_shard_range_lists_under_threads(P):
+    """Two host threads calling with many distinct ranges at once (every call
+    builds or reuses a cached T list; the cache keeps eight, so lists are evicted
+    while the other thread may hold one): every result equals the same slice of
+    a single whole-order call, bit for bit."""
+    import threading
+    import torch
+    _say("case: shard T lists under two threads, M=13 order 5")
+    inst = G.make_instance("m144_k5", M=13, seed=13)
+    s = _dev(inst.sigma)
+    n = math.comb(13, 5)
+    c_ref, k_ref = P.gbs_cumulants_shard(13, s, 5, 0, n, 0)
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(tid):
+        try:
+            for rnd in range(2):
+                for i in range(12):
+                    r0 = (37 * i + 11 * tid + rnd) % (n - 40)
+                    cnt = 1 + (53 * i + 17 * tid) % (n - r0)
+                    c, k = P.gbs_cumulants_shard(13, s, 5, r0, cnt, 0)
+                    torch.cuda.synchronize()
+                    if not (torch.equal(c, c_ref[r0:r0 + cnt]) and torch.equal(k, k_ref[r0:r0 + cnt])):
+                        errors.append((tid, rnd, r0, cnt))
+        except Exception as e:  # reported below
+            errors.append((tid, repr(e)))
+
+    ts = [threading.Thread(target=work, args=(t,)) for t in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errors, errors[:5]
