@@ -34,7 +34,8 @@ Bit decision: with u_n ~ U[0, 1) supplied by the caller, x_n = 1 when
 u_n < p(x_n = 1 | x_{<n}) = p(x_n = 1, x_{n-1}, ..., x_1) / p(n - 1), the
 expansion's value over the previously computed p(n - 1).  The expansion may
 leave [0, 1]: the comparison then clamps it; when p(n - 1) is not positive the
-conditional is undefined and 1/2 is used (both readings are this build's).
+conditional is undefined and 1/2 is used (the paper fixes neither case; both
+are readings of it).
 All arithmetic is FP64.
 """
 from __future__ import annotations
