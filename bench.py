@@ -633,8 +633,10 @@ def main():
                     help="only run a plain device-to-device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: the path needs no communication and every "
-              "figure here is per GPU (see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: every figure here is per GPU.  The path needs "
+              "no communication; on several GPUs each would take a contiguous slice of every "
+              "order's colex ranks (gbs_cumulants_shard) after one broadcast of sigma",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

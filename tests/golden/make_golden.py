@@ -24,7 +24,7 @@ def main():
         np.savez(os.path.join(HERE, f"m16_k3_{tag}.npz"), sigma=inst.sigma, corr=corr, cum=cum)
     # closed forms: TMSV pair (r -> tanh^2 r, tanh^2 r sech^2 r)
     with open(os.path.join(HERE, "closed_forms.txt"), "w") as f:
-        f.write("# closed-form values (see README.md for the passages they follow)\n")
+        f.write("# closed-form values (tests/golden/README.md gives the passages they follow)\n")
         f.write("# kind r eta mu kappa\n")
         for r in (0.3, 0.8, 1.3):
             t2 = math.tanh(r) ** 2
