@@ -213,7 +213,8 @@ GBS_API gbs_status gbs_cumulants_displaced(int32_t M, const double* sigma, const
  * side lists the range's T's on the first call of a range and copies the list
  * to the device with a blocking copy (so that first call must not be captured
  * in a graph); the last eight lists stay on the device, and evicting one waits
- * for the device.  Ranges of more than 2^22 T's run the B-tiled kernel.  Orders 1, 2 and GBS_ALL_MINORS
+ * for the device.  A range of more than 2^16 T's runs as consecutive chunks of
+ * 2^16 T's, one list and one launch each.  Orders 1, 2 and GBS_ALL_MINORS
  * run the all-minors kernel of gbs_cumulants' GBS_ALL_MINORS, whose shards are
  * bit-identical to slices of that full pass.
  * Same definitions and tolerance as gbs_cumulants.

@@ -329,9 +329,9 @@ gbs_status run_shard(int32_t M, const double* sigma, int32_t d, int64_t rank0, i
   if (e == hipSuccess) e = launch_build_q(sigma, M, Qi, s);
   if (e == hipSuccess) e = timing_end(s);
   if (e == hipSuccess) e = timing_begin(s, GBS_STAGE_FORWARD, d);
-  // orders >= 3: the B-tiled kernel; orders 1, 2 and GBS_ALL_MINORS: the all-minors kernel
+  // orders >= 3: the T-shared kernel; orders 1, 2 and GBS_ALL_MINORS: the all-minors kernel
   if (e == hipSuccess && d >= 3 && !(flags & GBS_ALL_MINORS))
-    e = launch_forward_shard(d, M, flags, Qi, ctx->binom, (uint64_t)rank0, (uint64_t)count, corr,
+    e = launch_forward_shard(d, M, flags, Qi, (uint64_t)rank0, (uint64_t)count, corr,
                              cum, st, s);
   else if (e == hipSuccess)
     e = launch_forward_range(d, M, flags, Qi, ctx->binom, (uint64_t)rank0, (uint64_t)count, corr,

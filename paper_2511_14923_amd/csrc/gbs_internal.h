@@ -76,11 +76,12 @@ hipError_t launch_forward_range(int d, int M, int flags, const double* Qi, const
                                 uint64_t rank0, uint64_t count, double* corr, double* cum,
                                 DeviceStatus* st, hipStream_t s);
 
-// The same for orders 3..5 by the B-tiled kernel (gbs_forward_shard.hip): each
-// run of consecutive B's shares its part of the principal-minor recursion.
-hipError_t launch_forward_shard(int d, int M, int flags, const double* Qi, const uint64_t* binom,
-                                uint64_t rank0, uint64_t count, double* corr, double* cum,
-                                DeviceStatus* st, hipStream_t s);
+// The same for orders 3..5 by the T-shared kernel (gbs_forward_shard.hip): the
+// subsets {a, b_0} + T of one T share the factors of Q_T, of each b_0 and of
+// each a against T.  The range runs as consecutive chunks of at most 2^16 T's.
+hipError_t launch_forward_shard(int d, int M, int flags, const double* Qi, uint64_t rank0,
+                                uint64_t count, double* corr, double* cum, DeviceStatus* st,
+                                hipStream_t s);
 
 // Lower-order tables read by the order-recursive kernels: p[q], m[q], k[q]
 // point at the order-q blocks (q below the order being computed).

@@ -157,3 +157,48 @@ def test_shard_range_lists_under_threads(P):
     for t in ts:
         t.join()
     assert not errors, errors[:5]
+
+
+def _chunk_starts(M, order, max_t=1 << 16):
+    """Ranks at which a whole-order range starts a new chunk of at most max_t T's
+    (T in colex order, those with a nonempty triangle a < b_0 < min T)."""
+    import itertools
+    nt = order - 2
+    starts, k = [], 0
+    # colex order of the T's: sort by the reversed tuple
+    ts = sorted(itertools.combinations(range(M), nt), key=lambda t: t[::-1])
+    for t in ts:
+        if math.comb(t[0], 2) == 0:
+            continue
+        if k and k % max_t == 0:
+            starts.append(sum(math.comb(t[j], j + 3) for j in range(nt)))
+        k += 1
+    return starts
+
+
+def test_shard_in_chunks_m100(P):
+    """Order 5 at M = 100 (161,700 T's) runs as three chunks of at most 2^16 T's:
+    outputs around both chunk boundaries against the oracle, and ranges that
+    straddle a boundary equal to the same slice of the whole-order call, bit
+    for bit."""
+    import torch
+    _say("case: shard in chunks M=100 order 5")
+    inst = G.make_instance("m144_k5", M=100, seed=7)
+    s = _dev(inst.sigma)
+    n = math.comb(100, 5)
+    starts = _chunk_starts(100, 5)
+    assert len(starts) == 2, starts
+    c, k = P.gbs_cumulants_shard(100, s, 5, 0, n, 0)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    local = np.unique(np.concatenate([np.arange(b - 300, b + 300) for b in starts] +
+                                     [rng.integers(0, n, size=1500), np.arange(n - 50, n)]))
+    rc, rk = O.c_forward_sample(inst.sigma, 5, local)
+    smu, skap = fp64_scales(inst.sigma, 5, local)
+    assert_within(c.cpu().numpy()[local], rc, fp64_tolerance(rc, smu), "M=100 chunks corr")
+    assert_within(k.cpu().numpy()[local], rk, fp64_tolerance(rk, skap), "M=100 chunks cum")
+    for b in starts:
+        r0, cnt = b - 777, 2000
+        c2, k2 = P.gbs_cumulants_shard(100, s, 5, r0, cnt, 0)
+        torch.cuda.synchronize()
+        assert torch.equal(c2, c[r0:r0 + cnt]) and torch.equal(k2, k[r0:r0 + cnt]), b
