@@ -202,3 +202,32 @@ def test_shard_in_chunks_m100(P):
         c2, k2 = P.gbs_cumulants_shard(100, s, 5, r0, cnt, 0)
         torch.cuda.synchronize()
         assert torch.equal(c2, c[r0:r0 + cnt]) and torch.equal(k2, k[r0:r0 + cnt]), b
+
+
+@pytest.mark.parametrize("case", ["pivot", "coupling"])
+def test_shard_not_spd_reported(P, case):
+    """A non-physical covariance: GBS_E_NOT_SPD and a failing subset that holds
+    the bad modes.  "pivot": mode 2 has negative variances, caught in the
+    factors of T, b_0 or a; "coupling": modes 0 and 1 are each physical but
+    their x quadratures are coupled beyond positive definiteness, which only the
+    main loop's pair leaves (a = 0, b_0 = 1) can see."""
+    import torch
+    _say("case: shard not SPD", case)
+    M = 8
+    sigma = G.vacuum_covariance(M)
+    if case == "pivot":
+        sigma[2, 2] = sigma[2 + M, 2 + M] = -0.9
+        bad = {2}
+    else:
+        sigma[0, 1] = sigma[1, 0] = 1.5  # Q restricted to (x_0, x_1): [[1, 1.5], [1.5, 1]]
+        bad = {0, 1}
+    s = torch.from_numpy(sigma).to("cuda:0")
+    with pytest.raises(P.GBSError) as ei:
+        P.gbs_cumulants_shard(M, s, 5, 0, math.comb(M, 5), 0)
+    assert ei.value.status == P.GBS_E_NOT_SPD
+    st, order, rank = P.gbs_last_error()
+    assert st == P.GBS_E_NOT_SPD and order == 5
+    assert bad <= set(P.gbs_colex_unrank(5, rank))
+    P.gbs_cumulants_shard(M, torch.from_numpy(G.vacuum_covariance(M)).to("cuda:0"), 5, 0,
+                          math.comb(M, 5), 0)
+    assert P.gbs_last_error()[0] == P.GBS_OK
