@@ -15,7 +15,7 @@
 //     reduced by the eliminated blocks), eliminating block t gives
 //       S' = S - C_t^T P^{-1} C_t,    C_rest' = C_rest - u^T C_t,
 //     dropping it leaves both unchanged; each elimination edge keeps
-//     w = P_t^{-1} C_t, each leaf V keeps (S_b0|V)^{-1} and
+//     w = P_t^{-1} C_t, each leaf V keeps the inverse Cholesky factor of S_b0|V and
 //     p({b_0} + V) = p(V) det(S_b0|V)^(-1/2) (det(Q_{V+b}) = det(Q_V) det(S));
 //     then m(W) for every W subset of B (subset zeta transform) and the
 //     coefficients c_B(U) of the cumulant as a linear form in the p({a} + U)
@@ -25,7 +25,7 @@
 //     and p({a} + V);
 //   main loop, lane = a, over the b_0: the cross block G = Q_{b_0, a} goes
 //     down the tree, G <- G - w^T C_t^a at every elimination edge, and at leaf V
-//       S_a|{b_0}+V = S_a|V - G^T (S_b0|V)^{-1} G,
+//       S_a|{b_0}+V = S_a|V - G^T (S_b0|V)^{-1} G = S_a|V - H^T H, H = L^{-1} G,
 //       p({a, b_0} + V) = p({b_0} + V) det(S_a|{b_0}+V)^(-1/2);
 //     then m(S) = m(B) - nu(B) with nu(B) = sum_U s(U) p({a} + U) (parity:
 //     -m(B) + 2 (-1)^|B| nu(B); Eq. corre_cov_main split by whether the subset
@@ -144,9 +144,9 @@ __host__ __device__ inline uint32_t ts_tiles(uint32_t b0lo, uint32_t b0hi, int64
   return n;
 }
 
-// Per-b_0 record in LDS, doubles: edges (w, 4 each), leaves ((S_b0|V)^{-1}
-// packed lower, then p({b_0} + V)), c_B(U) (bit 0 of U: b_0, bit k + 1: T
-// block k), m(B), a failure flag.
+// Per-b_0 record in LDS, doubles: edges (w, 4 each), leaves (the inverse
+// Cholesky factor of S_b0|V packed lower, then p({b_0} + V)), c_B(U) (bit 0 of
+// U: b_0, bit k + 1: T block k), m(B), a failure flag.
 template <int NT>
 struct TsRec {
   static constexpr int NV = 1 << NT;
@@ -160,7 +160,9 @@ struct TsRec {
   static constexpr int stride = (oBad + 2) & ~1;
 };
 
-// Leaf V of the bordered recursion: B0 keeps (S^{-1}, p), otherwise (S, p).
+// Leaf V of the bordered recursion: B0 keeps (L^{-1}, p) with S = L L^T
+// (L^{-1} = [[r, 0], [-s10 r y, s00 r y]], r = s00^(-1/2), y = det(S)^(-1/2)),
+// otherwise (S, p).
 template <unsigned V, bool B0>
 __device__ __forceinline__ void ts_leaf(const double* pT, double s00, double s10, double s11,
                                         double* lr, bool& bad) {
@@ -169,10 +171,11 @@ __device__ __forceinline__ void ts_leaf(const double* pT, double s00, double s10
   const double y = rsqrt_f64(det);
   double* l = lr + 4 * V;
   if constexpr (B0) {
-    const double id = y * y;
-    l[0] = s11 * id;
-    l[1] = -s10 * id;
-    l[2] = s00 * id;
+    const double r = rsqrt_f64(s00);
+    const double ry = r * y;
+    l[0] = r;
+    l[1] = -s10 * ry;
+    l[2] = s00 * ry;
   } else {
     l[0] = s00;
     l[1] = s10;
@@ -233,7 +236,9 @@ __device__ __forceinline__ void ts_border(const double* tn, const double* pT,
   }
 }
 
-// Leaf V of the main loop: p({a, b_0} + V) from G, the b_0 record and S_a|V.
+// Leaf V of the main loop: p({a, b_0} + V) from G, the b_0 record and S_a|V:
+// with H = L^{-1} G, S_a|{b_0}+V = S_a|V - H^T H.  Its diagonal is at most that
+// of S_a|V, which phase C found finite, so a finite determinant needs no check.
 template <int NT, unsigned V>
 __device__ __forceinline__ void ts_pair_leaf(const double* br, const double (&sa)[1 << NT][3],
                                              double g00, double g01, double g10, double g11,
@@ -242,16 +247,16 @@ __device__ __forceinline__ void ts_pair_leaf(const double* br, const double (&sa
   const double* l = br + R::oL + 4 * V;
   const double2 iv = *reinterpret_cast<const double2*>(l);
   const double2 lp = *reinterpret_cast<const double2*>(l + 2);
-  const double i00 = iv.x, i10 = iv.y, i11 = lp.x;
-  const double h00 = fma(i00, g00, i10 * g10);
-  const double h01 = fma(i00, g01, i10 * g11);
-  const double h10 = fma(i10, g00, i11 * g10);
-  const double h11 = fma(i10, g01, i11 * g11);
-  const double s00 = fma(-g00, h00, fma(-g10, h10, sa[V][0]));
-  const double s10 = fma(-g01, h00, fma(-g11, h10, sa[V][1]));
-  const double s11 = fma(-g01, h01, fma(-g11, h11, sa[V][2]));
+  const double r = iv.x, m = iv.y, q = lp.x;
+  const double h00 = r * g00;
+  const double h01 = r * g01;
+  const double h10 = fma(m, g00, q * g10);
+  const double h11 = fma(m, g01, q * g11);
+  const double s00 = fma(-h00, h00, fma(-h10, h10, sa[V][0]));
+  const double s10 = fma(-h00, h01, fma(-h10, h11, sa[V][1]));
+  const double s11 = fma(-h01, h01, fma(-h11, h11, sa[V][2]));
   const double det = fma(s00, s11, -s10 * s10);
-  bad |= !(s00 > 0.0) || !(det > 0.0) || !(det < INFINITY);
+  bad |= !(s00 > 0.0) || !(det > 0.0);
   pab[V] = lp.y * rsqrt_f64(det);
 }
 
