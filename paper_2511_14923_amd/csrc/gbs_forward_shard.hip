@@ -105,10 +105,10 @@ __device__ __forceinline__ void b_tree(const Tri<2 * (NB - K)>& A, double pT, do
 }
 
 // a's per tile: one wavefront.  b_0's per tile: 30 records (19.1 KB of LDS at
-// order 5) let the eight one-wavefront workgroups that the order-5 kernel's 246
-// VGPRs allow share a compute unit (M = 1152 order-5 shard: 16 / 24 / 30 / 32
-// b_0's 8.3 / 8.1 / 7.8 / 7.8 ms; capping the registers for a third wave per
-// SIMD spills and takes 25 ms).
+// order 5) let the eight one-wavefront workgroups that the order-5 kernel's
+// registers allow (over 168: two waves per SIMD) share a compute unit (M = 1152
+// order-5 shard: 16 / 24 / 30 / 32 b_0's 8.3 / 8.1 / 7.8 / 7.8 ms; capping the
+// registers for a third wave per SIMD spills and takes 25 ms).
 constexpr int kTsA = 64;
 constexpr int kTsB = 30;
 
